@@ -1,0 +1,264 @@
+/*
+ * pir.h -- C ABI of the MI355X dpXOR library (libpir.so).
+ *
+ * dpXOR is the server-side hot path of DPF-based two-server private
+ * information retrieval (IM-PIR, Sec. 2 "Multi-Server PIR" and Sec. 3.3
+ * "PIR linear operations"): given a resident database D of N records of R
+ * bytes and a selection bit vector v in F_2^N (a DPF key share expanded over
+ * the whole domain, v[j] = Eval(k, j)), the server returns
+ *
+ *     r = XOR over j = 0 .. N-1 of v[j] * D[j]          (an R-byte record)
+ *
+ * The client XORs the two servers' answers to recover D[i].
+ *
+ * Conventions shared by every call:
+ *  - Record j is bytes [j*R, (j+1)*R) of a row-major host buffer.
+ *  - Bit j of a selection vector is (sel[j >> 3] >> (j & 7)) & 1 (LSB first).
+ *    Bits at positions >= N are ignored (they may hold anything).
+ *  - A batch of Q selection vectors is Q rows `sel_stride` bytes apart; row q
+ *    of the answer is r for row q alone (queries are independent, Sec. 3.4).
+ *  - Every call returns PIR_OK (0) or a negative pir_status; on failure
+ *    nothing is half done (a failed load frees what it allocated) and
+ *    pir_last_error() returns a message for the calling thread.
+ *  - There is no CPU fallback: without a usable gfx950 device, calls fail
+ *    with PIR_E_DEVICE.
+ */
+#ifndef PIR_H
+#define PIR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pir_ctx pir_ctx;
+typedef struct pir_db pir_db;
+typedef struct pir_server pir_server;
+
+typedef enum pir_status {
+    PIR_OK = 0,
+    PIR_E_INVAL = -1,    /* bad argument: NULL, N = 0, R = 0, size overflow, Q out of range */
+    PIR_E_NOMEM = -2,    /* device or pinned allocation failed, or over the HBM budget */
+    PIR_E_DEVICE = -3,   /* a HIP call failed; the message names it */
+    PIR_E_BUSY = -4,     /* a serving queue is full */
+    PIR_E_NOTFOUND = -5, /* unknown database id or ticket */
+    PIR_E_SHUTDOWN = -6, /* the server is shutting down; the request was not run */
+    PIR_E_TIMEOUT = -7   /* pir_serve_wait timed out; the request is still pending */
+} pir_status;
+
+/* Largest batch a single call accepts. */
+#define PIR_MAX_BATCH 4096u
+
+/* Kernel variants for the batched scan (pir_kernel_cfg.variant). */
+#define PIR_VARIANT_AUTO 0u     /* autotuned choice (cached per shape) */
+#define PIR_VARIANT_VALU 1u     /* bitwise select-XOR on the vector ALUs */
+#define PIR_VARIANT_MFMA_I8 2u  /* GF(2) contraction on int8 MFMA, exact int32, then mod 2 */
+#define PIR_VARIANT_MFMA_F4 3u  /* GF(2) contraction on fp4 MFMA, exact fp32 counts, then mod 2 */
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char* pir_last_error(void);
+
+/* Library version string. */
+const char* pir_version(void);
+
+/* ---------------------------------------------------------------- context */
+
+/* Bind to HIP device `hip_device` (must be gfx950).  The context owns the
+ * streams, workspaces and pinned staging buffers used by the sync calls. */
+int pir_ctx_create(int hip_device, pir_ctx** out);
+int pir_ctx_destroy(pir_ctx* ctx);
+
+/* ---------------------------------------------------------------- database */
+
+/*
+ * Database preload (IM-PIR Sec. 3.3 "Database preloading": the database is
+ * resident before any query and its transfer is not part of a query).
+ * Copies n_records x record_bytes bytes from the host buffer `records` into
+ * HBM.  The caller may free `records` on return; the library owns the device
+ * copy until pir_db_free.  The device copy is stored bit-sliced: each block
+ * of 32 consecutive records becomes 8*R 32-bit words, word b holding bit b of
+ * the 32 records (record 32*blk+i at bit i), with records past N zero.
+ * Errors: PIR_E_INVAL (NULL, N = 0, R = 0, N*R overflow), PIR_E_NOMEM.
+ */
+int pir_db_load(pir_ctx* ctx, const void* records, uint64_t n_records, uint32_t record_bytes,
+                pir_db** out);
+
+/*
+ * Bulk update of records [first, first + count) from a host buffer (the
+ * idle-window update of Sec. 3.3).  Must not overlap a scan of the same
+ * database; it synchronises with the context's own calls only.
+ */
+int pir_db_update(pir_db* db, uint64_t first, uint64_t count, const void* records);
+
+/* Copy records [first, first + count) back to the host in row-major form. */
+int pir_db_read(pir_db* db, uint64_t first, uint64_t count, void* out_records);
+
+int pir_db_free(pir_db* db);
+
+typedef struct pir_db_info {
+    uint64_t n_records;     /* N */
+    uint32_t record_bytes;  /* R */
+    uint32_t reserved;
+    uint64_t n_blocks;      /* ceil(N / 32) bit-sliced blocks */
+    uint64_t device_bytes;  /* HBM held by the database */
+    uint64_t sel_words;     /* 32-bit selection words per query row (= n_blocks) */
+} pir_db_info;
+
+int pir_db_get_info(const pir_db* db, pir_db_info* out);
+
+/* Minimum device selection-row stride in bytes for the async calls:
+ * 4 * ceil(N / 32), i.e. whole 32-bit words covering every block. */
+uint64_t pir_db_min_sel_stride(const pir_db* db);
+
+/* ---------------------------------------------------------------- scans */
+
+/*
+ * One query, synchronous: sel_bits is a host buffer of ceil(N/8) bytes;
+ * out_record receives R bytes.  Uploads the selection, runs the scan and
+ * downloads the answer on a pooled stream; safe to call from several threads
+ * on the same database.
+ */
+int pir_dpxor(pir_db* db, const uint8_t* sel_bits, uint8_t* out_record);
+
+/*
+ * Q queries in one database pass, synchronous.  sel_bits holds q rows
+ * sel_stride bytes apart (sel_stride >= ceil(N/8)); out receives q rows of R
+ * bytes.  1 <= q <= PIR_MAX_BATCH.
+ */
+int pir_dpxor_batch(pir_db* db, const uint8_t* sel_bits, uint64_t sel_stride, uint32_t q,
+                    uint8_t* out);
+
+/*
+ * Q queries, asynchronous on a caller stream, device buffers only (for
+ * example torch tensors).  d_sel: q rows of 32-bit words, sel_stride bytes
+ * apart, sel_stride a multiple of 4 and >= pir_db_min_sel_stride(db), base
+ * 4-byte aligned; bits of blocks past N are ignored.  d_out: q*R bytes.
+ * hip_stream: a hipStream_t (NULL = the null stream).  The call enqueues the
+ * scan and the cross-workgroup reduction and returns; d_out is valid once the
+ * stream reaches that point.  The library keeps one scratch workspace per
+ * stream, so overlapping calls on one stream are ordered and safe; it may
+ * synchronise the stream once to grow that workspace.
+ */
+int pir_dpxor_batch_async(pir_db* db, const void* d_sel, uint64_t sel_stride, uint32_t q,
+                          void* d_out, void* hip_stream);
+
+/* Explicit kernel configuration (tests of tile invariance, the autotuner). */
+typedef struct pir_kernel_cfg {
+    uint32_t variant; /* PIR_VARIANT_* */
+    uint32_t q_tile;  /* queries per workgroup tile (variant-specific; 0 = default) */
+    uint32_t unroll;  /* blocks per wave iteration (0 = default) */
+    uint32_t groups;  /* record groups = partial results per query (0 = default) */
+} pir_kernel_cfg;
+
+/* As pir_dpxor_batch_async, with an explicit configuration.  Unsupported
+ * combinations return PIR_E_INVAL. */
+int pir_dpxor_batch_async_cfg(pir_db* db, const void* d_sel, uint64_t sel_stride, uint32_t q,
+                              void* d_out, void* hip_stream, const pir_kernel_cfg* cfg);
+
+/* Configuration the library would use for q queries on db (after tuning). */
+int pir_get_cfg(pir_db* db, uint32_t q, pir_kernel_cfg* out);
+
+/*
+ * Autotuner: times each candidate configuration for q queries on this
+ * database (device-resident scratch selections), keeps the fastest in the
+ * context's cache, keyed by (architecture, R, Q bucket, N bucket), and
+ * writes the cache to the JSON file named by the PIR_TUNE_CACHE environment
+ * variable if set.  Returns the chosen configuration in *out (may be NULL).
+ */
+int pir_tune(pir_db* db, uint32_t q, pir_kernel_cfg* out);
+
+/* ---------------------------------------------------------------- timing */
+
+/*
+ * Kernel timing: while enabled, the library records HIP events on the
+ * launch stream around every scan kernel (stage 1) and reduction kernel
+ * (stage 2) it launches.  pir_timing_read waits for the recorded events and
+ * returns the launch counts and summed durations since the last reset.
+ */
+typedef struct pir_timing {
+    uint64_t stage1_launches;
+    double stage1_ms;
+    uint64_t stage2_launches;
+    double stage2_ms;
+} pir_timing;
+
+int pir_timing_enable(pir_ctx* ctx, int on);
+int pir_timing_read(pir_ctx* ctx, pir_timing* out, int reset);
+
+/* ---------------------------------------------------------------- serving */
+
+/*
+ * Continuous-batching server (IM-PIR Sec. 3.4 "Batching client queries":
+ * queries queue up and are dispatched to execution resources as they free
+ * up).  Several databases stay resident; requests are queued per database;
+ * a scheduler thread packs up to q_max pending requests of one database into
+ * a free slot (its own stream, pinned buffers and workspace) and launches
+ * one batched scan; requests that arrive meanwhile join later batches.
+ * Slots run concurrently on the device.
+ */
+typedef struct pir_serve_config {
+    uint64_t hbm_budget_bytes; /* admission limit for resident databases + slot buffers (0 = no limit) */
+    uint32_t q_max;            /* largest batch per launch (<= PIR_MAX_BATCH; 0 = 64) */
+    uint32_t max_wait_us;      /* a partial batch waits at most this long for company (0 = dispatch at once) */
+    uint32_t n_slots;          /* concurrent in-flight batches (0 = 4) */
+    uint32_t queue_cap;        /* pending requests per database before PIR_E_BUSY (0 = 65536) */
+} pir_serve_config;
+
+typedef struct pir_serve_stats {
+    uint64_t submitted;
+    uint64_t completed;
+    uint64_t rejected;        /* PIR_E_BUSY / PIR_E_SHUTDOWN at submit */
+    uint64_t batches;
+    double p50_us;            /* submit -> answer in host memory */
+    double p99_us;
+    double mean_us;
+    double max_us;
+    double elapsed_s;         /* since create or the last reset */
+    double qps;               /* completed / elapsed_s */
+    uint64_t batch_hist[13];  /* batches with size in [2^i, 2^(i+1)) */
+    uint64_t h2d_bytes;       /* selection bytes uploaded */
+} pir_serve_stats;
+
+int pir_serve_create(pir_ctx* ctx, const pir_serve_config* cfg, pir_server** out);
+
+/* Admit a loaded database (PIR_E_NOMEM if it would exceed the budget).  The
+ * database must outlive the server. */
+int pir_serve_add_db(pir_server* srv, pir_db* db, uint32_t* db_id);
+
+/*
+ * Queue one query.  sel_bits (ceil(N/8) bytes) is copied before the call
+ * returns; out (R bytes) must stay valid until pir_serve_wait or
+ * pir_serve_poll reports completion.  Errors: PIR_E_NOTFOUND (db_id),
+ * PIR_E_BUSY (queue full), PIR_E_SHUTDOWN.
+ */
+int pir_serve_submit(pir_server* srv, uint32_t db_id, const uint8_t* sel_bits, uint8_t* out,
+                     uint64_t* ticket);
+
+/* Wait for a ticket: PIR_OK once out holds the answer, the request's own
+ * error, PIR_E_TIMEOUT, or PIR_E_NOTFOUND for an unknown or already
+ * collected ticket.  timeout_ms < 0 waits forever. */
+int pir_serve_wait(pir_server* srv, uint64_t ticket, int timeout_ms);
+
+/* Non-blocking: 1 if done (result in *status), 0 if pending. */
+int pir_serve_poll(pir_server* srv, uint64_t ticket, int* status);
+
+int pir_serve_stats_get(pir_server* srv, pir_serve_stats* out, int reset);
+
+/* Stop accepting requests, finish everything queued or in flight, join the
+ * scheduler and free the slots.  Every ticket completes or reports
+ * PIR_E_SHUTDOWN; none is lost. */
+int pir_serve_destroy(pir_server* srv);
+
+/* ---------------------------------------------------------------- memory */
+
+/* Pinned host memory (hipHostMalloc); NULL on failure. */
+void* pir_host_alloc(size_t bytes);
+void pir_host_free(void* p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIR_H */

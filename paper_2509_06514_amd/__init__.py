@@ -1,0 +1,252 @@
+"""MI355X dpXOR: the server-side scan of DPF-based two-server PIR (IM-PIR).
+
+A thin Python binding over libpir.so (include/pir.h).  Every step of the
+scan runs in the library's HIP kernels; this module only marshals arguments.
+torch supplies device buffers and streams for the asynchronous calls.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _native
+from ._native import (PIR_MAX_BATCH, PIR_VARIANT_AUTO, PIR_VARIANT_MFMA_F4, PIR_VARIANT_MFMA_I8,
+                      PIR_VARIANT_VALU, PirError, check, lib)
+
+__all__ = ["Context", "Database", "Server", "KernelCfg", "PirError", "lib", "sel_stride_for",
+           "PIR_MAX_BATCH", "PIR_VARIANT_AUTO", "PIR_VARIANT_VALU", "PIR_VARIANT_MFMA_I8",
+           "PIR_VARIANT_MFMA_F4"]
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _u8(a):
+    a = np.asarray(a)
+    if a.dtype != np.uint8:
+        a = a.view(np.uint8) if a.dtype.itemsize == 1 else a.astype(np.uint8)
+    return np.ascontiguousarray(a)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+class KernelCfg:
+    """Explicit stage-1 configuration (variant, query tile, unroll, record groups)."""
+
+    def __init__(self, variant=PIR_VARIANT_AUTO, q_tile=0, unroll=0, groups=0):
+        self.variant, self.q_tile, self.unroll, self.groups = variant, q_tile, unroll, groups
+
+    def _c(self):
+        return _native.pir_kernel_cfg(self.variant, self.q_tile, self.unroll, self.groups)
+
+    @classmethod
+    def _from_c(cls, c):
+        return cls(c.variant, c.q_tile, c.unroll, c.groups)
+
+    def as_dict(self):
+        return {"variant": self.variant, "q_tile": self.q_tile, "unroll": self.unroll,
+                "groups": self.groups}
+
+    def __repr__(self):
+        return f"KernelCfg({self.as_dict()})"
+
+
+def sel_stride_for(n_records, align=256):
+    """Device selection-row pitch: whole 32-bit words for ceil(N/32) blocks, aligned."""
+    words = (n_records + 31) // 32
+    return (4 * words + align - 1) // align * align
+
+
+class Context:
+    """A device context (pir_ctx)."""
+
+    def __init__(self, device=0):
+        h = ctypes.c_void_p()
+        check(lib().pir_ctx_create(device, ctypes.byref(h)), "pir_ctx_create")
+        self._h = h
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def load_db(self, records, n_records=None):
+        """Preload an (N, R) uint8 record array into HBM."""
+        records = _u8(records)
+        if records.ndim != 2:
+            raise ValueError("records must be (N, R)")
+        n, r = records.shape
+        if n_records is not None:
+            n = n_records
+        h = ctypes.c_void_p()
+        check(lib().pir_db_load(self._h, _ptr(records), n, r, ctypes.byref(h)), "pir_db_load")
+        return Database(self, h)
+
+    def timing(self, on=True):
+        check(lib().pir_timing_enable(self._h, 1 if on else 0), "pir_timing_enable")
+
+    def timing_read(self, reset=True):
+        t = _native.pir_timing()
+        check(lib().pir_timing_read(self._h, ctypes.byref(t), 1 if reset else 0), "pir_timing_read")
+        return {"stage1_launches": t.stage1_launches, "stage1_ms": t.stage1_ms,
+                "stage2_launches": t.stage2_launches, "stage2_ms": t.stage2_ms}
+
+    def close(self):
+        if self._h:
+            check(lib().pir_ctx_destroy(self._h), "pir_ctx_destroy")
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Database:
+    """A resident database (pir_db)."""
+
+    def __init__(self, ctx, handle):
+        self.ctx = ctx
+        self._h = handle
+        info = _native.pir_db_info()
+        check(lib().pir_db_get_info(handle, ctypes.byref(info)), "pir_db_get_info")
+        self.n_records = info.n_records
+        self.record_bytes = info.record_bytes
+        self.n_blocks = info.n_blocks
+        self.device_bytes = info.device_bytes
+        self.min_sel_stride = lib().pir_db_min_sel_stride(handle)
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def sel_row_bytes(self):
+        return (self.n_records + 7) // 8
+
+    def dpxor(self, sel):
+        """One query, host in/out: sel packed bits (>= ceil(N/8) bytes) -> R-byte answer."""
+        sel = _u8(sel).reshape(-1)
+        if sel.size < self.sel_row_bytes:
+            raise ValueError("selection shorter than ceil(N/8) bytes")
+        out = np.empty(self.record_bytes, np.uint8)
+        check(lib().pir_dpxor(self._h, _ptr(sel), _ptr(out)), "pir_dpxor")
+        return out
+
+    def dpxor_batch(self, sel_rows):
+        """Q queries, host in/out: sel_rows (Q, stride) uint8 -> (Q, R) answers."""
+        sel_rows = _u8(sel_rows)
+        q, stride = sel_rows.shape
+        out = np.empty((q, self.record_bytes), np.uint8)
+        check(lib().pir_dpxor_batch(self._h, _ptr(sel_rows), stride, q, _ptr(out)), "pir_dpxor_batch")
+        return out
+
+    def dpxor_batch_async(self, d_sel, q, d_out, sel_stride=None, stream=None, cfg=None):
+        """Q queries on device buffers (torch tensors), enqueued on `stream`.
+
+        d_sel: q rows of sel_stride bytes (a multiple of 4, >= min_sel_stride);
+        d_out: q*R bytes.
+        """
+        if sel_stride is None:
+            sel_stride = d_sel.stride(0) * d_sel.element_size() if d_sel.dim() == 2 else self.min_sel_stride
+        if d_sel.device.type != "cuda" or d_out.device.type != "cuda":
+            raise ValueError("device tensors required")
+        if d_sel.numel() * d_sel.element_size() < (q - 1) * sel_stride + self.min_sel_stride:
+            raise ValueError("d_sel too small")
+        if d_out.numel() * d_out.element_size() < q * self.record_bytes:
+            raise ValueError("d_out too small")
+        s = _stream_handle(stream)
+        if cfg is None:
+            rc = lib().pir_dpxor_batch_async(self._h, ctypes.c_void_p(d_sel.data_ptr()), sel_stride, q,
+                                             ctypes.c_void_p(d_out.data_ptr()), s)
+        else:
+            c = cfg._c()
+            rc = lib().pir_dpxor_batch_async_cfg(self._h, ctypes.c_void_p(d_sel.data_ptr()), sel_stride, q,
+                                                 ctypes.c_void_p(d_out.data_ptr()), s, ctypes.byref(c))
+        check(rc, "pir_dpxor_batch_async")
+
+    def get_cfg(self, q):
+        c = _native.pir_kernel_cfg()
+        check(lib().pir_get_cfg(self._h, q, ctypes.byref(c)), "pir_get_cfg")
+        return KernelCfg._from_c(c)
+
+    def tune(self, q):
+        c = _native.pir_kernel_cfg()
+        check(lib().pir_tune(self._h, q, ctypes.byref(c)), "pir_tune")
+        return KernelCfg._from_c(c)
+
+    def update(self, first, records):
+        records = _u8(records)
+        n = records.shape[0]
+        check(lib().pir_db_update(self._h, first, n, _ptr(records)), "pir_db_update")
+
+    def read(self, first, count):
+        out = np.empty((count, self.record_bytes), np.uint8)
+        check(lib().pir_db_read(self._h, first, count, _ptr(out)), "pir_db_read")
+        return out
+
+    def free(self):
+        if self._h:
+            check(lib().pir_db_free(self._h), "pir_db_free")
+            self._h = None
+
+
+class Server:
+    """Continuous-batching server (pir_server)."""
+
+    def __init__(self, ctx, hbm_budget_bytes=0, q_max=64, max_wait_us=0, n_slots=4, queue_cap=0):
+        cfg = _native.pir_serve_config(hbm_budget_bytes, q_max, max_wait_us, n_slots, queue_cap)
+        h = ctypes.c_void_p()
+        check(lib().pir_serve_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)), "pir_serve_create")
+        self._h = h
+        self._dbs = {}
+
+    def add_db(self, db):
+        i = ctypes.c_uint32()
+        check(lib().pir_serve_add_db(self._h, db.handle, ctypes.byref(i)), "pir_serve_add_db")
+        self._dbs[i.value] = db
+        return i.value
+
+    def submit(self, db_id, sel, out):
+        """Queue a query; `out` (R-byte uint8 array) is filled on completion."""
+        sel = _u8(sel)
+        t = ctypes.c_uint64()
+        check(lib().pir_serve_submit(self._h, db_id, _ptr(sel), _ptr(out), ctypes.byref(t)),
+              "pir_serve_submit")
+        return t.value
+
+    def submit_raw(self, db_id, sel_ptr, out_ptr):
+        t = ctypes.c_uint64()
+        rc = lib().pir_serve_submit(self._h, db_id, ctypes.c_void_p(sel_ptr), ctypes.c_void_p(out_ptr),
+                                    ctypes.byref(t))
+        return rc, t.value
+
+    def wait(self, ticket, timeout_ms=-1):
+        return lib().pir_serve_wait(self._h, ticket, timeout_ms)
+
+    def poll(self, ticket):
+        st = ctypes.c_int()
+        r = lib().pir_serve_poll(self._h, ticket, ctypes.byref(st))
+        if r < 0:
+            check(r, "pir_serve_poll")
+        return (r == 1), st.value
+
+    def stats(self, reset=False):
+        s = _native.pir_serve_stats()
+        check(lib().pir_serve_stats_get(self._h, ctypes.byref(s), 1 if reset else 0), "pir_serve_stats_get")
+        d = {k: getattr(s, k) for k, _ in s._fields_ if k != "batch_hist"}
+        d["batch_hist"] = list(s.batch_hist)
+        return d
+
+    def close(self):
+        if self._h:
+            check(lib().pir_serve_destroy(self._h), "pir_serve_destroy")
+            self._h = None

@@ -1,0 +1,74 @@
+// Internal declarations shared by the runtime, the kernels and the server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "pir.h"
+
+namespace pir {
+
+// Geometry of a bit-sliced database.
+//
+// Records are grouped in blocks of 32.  Block blk is 8*R 32-bit words; word b
+// holds bit b of the 32 records (bit b of a record = bit (b & 7) of byte
+// b >> 3; record 32*blk + i sits at bit i of the word).  A block is 32*R
+// bytes = 2*R 16-byte chunks.  Scans read whole chunks, one per lane.
+//
+//  - R >= 32 ("wide"): a wave covers 64 chunks (1 KiB, 256 bit columns) of one
+//    block per load; a block spans n_ct = ceil(2R/64) column tiles.  The
+//    query's selection word for the block is the same for the whole wave.
+//  - R < 32 ("narrow"): a wave covers bpw = floor(32/R) whole blocks per load
+//    (lpb = 2R lanes each); lanes past bpw*lpb idle.
+//
+// A "unit" is what one wave reads per load: 1 block (wide) or bpw blocks
+// (narrow).  The device allocation is rounded up to whole units; padding
+// blocks hold zero records.
+struct Geometry {
+    uint64_t n = 0;         // records
+    uint32_t R = 0;         // record bytes
+    uint32_t rpad = 0;      // R rounded up to 4 (partial-result row pitch)
+    uint64_t nb = 0;        // blocks holding records: ceil(n / 32)
+    uint32_t cpb = 0;       // 16-byte chunks per block = 2R
+    bool narrow = false;    // R < 32
+    uint32_t bpw = 1;       // blocks per unit
+    uint32_t lpb = 64;      // lanes per block (narrow: 2R)
+    uint32_t n_ct = 1;      // column tiles per block
+    uint32_t tile_bytes = 32;  // record bytes per column tile (narrow: R)
+    uint64_t n_units = 0;   // ceil(nb / bpw)
+    uint64_t nb_alloc = 0;  // n_units * bpw
+    uint64_t bytes() const { return nb_alloc * 32ull * R; }
+};
+
+Geometry make_geometry(uint64_t n, uint32_t R);
+
+// One launch of the stage-1 scan.
+struct Plan {
+    uint32_t variant = PIR_VARIANT_VALU;
+    uint32_t qt = 1;        // queries per tile
+    uint32_t unroll = 4;    // units per wave iteration
+    uint32_t groups = 1;    // record groups (contiguous unit ranges)
+    uint32_t n_qt = 1;      // query tiles
+    uint64_t units_per_group = 0;
+    uint32_t grid = 0;      // workgroups launched
+};
+
+// Kernel launchers (pir_kernels.hip).  All enqueue on `stream` and return the
+// launch status.
+bool valu_supported(uint32_t qt, uint32_t unroll);
+hipError_t launch_stage1_valu(const Geometry& g, const Plan& p, const void* db, const uint32_t* sel,
+                              uint64_t stride_words, uint32_t q, uint8_t* partials, hipStream_t s);
+bool mfma_supported(uint32_t variant, const Geometry& g, uint32_t qt, uint32_t unroll);
+hipError_t launch_stage1_mfma(const Geometry& g, const Plan& p, const void* db, const uint32_t* sel,
+                              uint64_t stride_words, uint32_t q, uint8_t* partials, hipStream_t s);
+hipError_t launch_stage2(const Geometry& g, uint32_t groups, uint32_t q, const uint8_t* partials,
+                         uint8_t* out, hipStream_t s);
+// natural row-major records [rec0, rec0 + nrec) -> bit-sliced blocks starting at rec0 / 32
+hipError_t launch_slice(const Geometry& g, const uint8_t* src, uint64_t nrec, uint32_t* dst_block0,
+                        uint64_t nblk, hipStream_t s);
+// bit-sliced blocks -> natural records (nrec valid records from block 0)
+hipError_t launch_unslice(const Geometry& g, const uint32_t* src_block0, uint64_t nblk, uint8_t* dst,
+                          uint64_t nrec, hipStream_t s);
+
+}  // namespace pir

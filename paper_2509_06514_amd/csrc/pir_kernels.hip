@@ -1,0 +1,369 @@
+// dpXOR kernels for gfx950 (CDNA4): bit-slicing transpose, the stage-1
+// database scan (select + XOR + in-workgroup reduction) and the stage-2
+// cross-workgroup reduction.
+//
+// The computation is r = XOR_j v[j] * D[j] (IM-PIR Sec. 3.3, "Inner products
+// and XORing operations").  Over the bit-sliced layout (see pir_internal.h)
+// bit b of r is the parity of  XOR over blocks of (W[blk][b] AND S[blk]),
+// where W[blk][b] is word b of the block and S[blk] the 32 selection bits of
+// the block's records.  Each lane keeps 32-bit XOR accumulators per bit
+// column; parities are taken once, at the end of a workgroup's range.  This
+// is the paper's two-stage parallel reduction (per-tasklet partials, then a
+// master XOR per DPU, then host aggregation), mapped to lanes, waves,
+// workgroups and a second kernel.
+#include <hip/hip_runtime.h>
+
+#include "pir_internal.h"
+
+namespace pir {
+
+namespace {
+
+constexpr int kThreads = 256;  // 4 waves of 64
+constexpr int kWaves = kThreads / 64;
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// One 16-byte chunk per lane (global_load_dwordx4); NT marks it streaming.
+template <bool NT>
+__device__ __forceinline__ u32x4 load16(const u32x4* p) {
+    if (NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+
+struct Stage1Params {
+    uint64_t n_units;
+    uint64_t units_per_group;
+    uint64_t stride_words;  // selection row pitch in 32-bit words
+    uint64_t nb;            // blocks holding records (selection words per row)
+    uint32_t q_total;
+    uint32_t groups;
+    uint32_t n_ct;
+    uint32_t n_qt;
+    uint32_t cpb;         // chunks per block
+    uint32_t bpw;         // blocks per unit
+    uint32_t lpb;         // lanes per block
+    uint32_t tile_bytes;  // record bytes per column tile
+    uint32_t R;
+    uint32_t rpad;
+};
+
+__device__ __forceinline__ uint32_t parity4(const u32x4& a) {
+    return (__builtin_popcount(a.x) & 1u) | ((__builtin_popcount(a.y) & 1u) << 1) |
+           ((__builtin_popcount(a.z) & 1u) << 2) | ((__builtin_popcount(a.w) & 1u) << 3);
+}
+
+// acc ^= d & s on four words (the compiler fuses each into one v_bitop3_b32).
+__device__ __forceinline__ void sel_xor(u32x4& acc, const u32x4& d, uint32_t s) { acc ^= d & s; }
+
+// Workgroup -> (record group, column tile, query tile).  Workgroups are
+// dispatched round-robin over the 8 XCDs; consecutive workgroups on one XCD
+// get the column/query tiles of the same record group, so the selection
+// words and database chunks they share meet in that XCD's L2.
+__device__ __forceinline__ bool decode_block(uint32_t groups, uint32_t n_ct, uint32_t n_qt,
+                                             uint32_t& group, uint32_t& ct, uint32_t& qt) {
+    const uint32_t total = groups * n_ct * n_qt;
+    const uint32_t per_xcd = (total + 7) / 8;
+    const uint32_t v = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (v >= total) return false;
+    const uint32_t co = n_ct * n_qt;
+    group = v / co;
+    const uint32_t rem = v - group * co;
+    ct = rem / n_qt;
+    qt = rem - ct * n_qt;
+    return true;
+}
+
+// Stage 1, vector-ALU variant.  QT queries per workgroup, U units per wave
+// iteration (U independent 16-byte loads in flight per lane).
+template <int QT, int U, bool NARROW>
+__global__ void __launch_bounds__(kThreads)
+k_stage1_valu(const u32x4* __restrict__ db, const uint32_t* __restrict__ sel,
+              uint8_t* __restrict__ partials, Stage1Params p) {
+    __shared__ uint8_t nib[kWaves][QT][64];
+
+    uint32_t group, ct, qt;
+    if (!decode_block(p.groups, p.n_ct, p.n_qt, group, ct, qt)) return;
+
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t q0 = qt * QT;
+
+    // lane -> (block within unit, chunk within block); idle lanes read chunk 0
+    // of a valid block and their accumulators are never reported.
+    uint32_t bi = 0, cc;
+    if (NARROW) {
+        bi = lane / p.lpb;
+        cc = lane - bi * p.lpb;
+        if (bi >= p.bpw) { bi = 0; cc = 0; }
+    } else {
+        cc = ct * 64 + lane;
+        if (cc >= p.cpb) cc = 0;
+    }
+    const uint64_t unit_chunks = (uint64_t)p.bpw * p.cpb;
+    const u32x4* dl = db + (uint64_t)bi * p.cpb + cc;
+
+    const uint32_t* srow[QT];
+#pragma unroll
+    for (int q = 0; q < QT; ++q) {
+        const uint32_t qq = (q0 + q < p.q_total) ? q0 + q : q0;
+        srow[q] = sel + (uint64_t)qq * p.stride_words;
+    }
+
+    u32x4 acc[QT];
+#pragma unroll
+    for (int q = 0; q < QT; ++q) acc[q] = u32x4{0, 0, 0, 0};
+
+    const uint64_t u_begin = (uint64_t)group * p.units_per_group;
+    const uint64_t u_end = (u_begin + p.units_per_group < p.n_units) ? u_begin + p.units_per_group
+                                                                     : p.n_units;
+    uint64_t u = u_begin + (uint64_t)wave * U;
+    for (; u + U <= u_end; u += (uint64_t)kWaves * U) {
+        u32x4 d[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) d[k] = load16<true>(dl + (u + k) * unit_chunks);
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if (NARROW) {
+                uint64_t blk = (u + k) * p.bpw + bi;
+                blk = blk < p.nb ? blk : p.nb - 1;  // padding blocks are zero: any word will do
+#pragma unroll
+                for (int q = 0; q < QT; ++q) sel_xor(acc[q], d[k], srow[q][blk]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < QT; ++q) sel_xor(acc[q], d[k], srow[q][u + k]);
+            }
+        }
+    }
+    // this wave's last, partial iteration
+    for (uint32_t k = 0; k < (uint32_t)U && u + k < u_end; ++k) {
+        const u32x4 dk = load16<true>(dl + (u + k) * unit_chunks);
+        if (NARROW) {
+            uint64_t blk = (u + k) * p.bpw + bi;
+            blk = blk < p.nb ? blk : p.nb - 1;
+#pragma unroll
+            for (int q = 0; q < QT; ++q) sel_xor(acc[q], dk, srow[q][blk]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < QT; ++q) sel_xor(acc[q], dk, srow[q][u + k]);
+        }
+    }
+
+    // Per-lane parity of each accumulated bit column, then XOR across waves
+    // (and, for narrow records, across the blocks of a unit).
+#pragma unroll
+    for (int q = 0; q < QT; ++q) nib[wave][q][lane] = (uint8_t)parity4(acc[q]);
+    __syncthreads();
+
+    const uint32_t tb = p.tile_bytes;
+    for (uint32_t t = threadIdx.x; t < QT * tb; t += kThreads) {
+        const uint32_t q = t / tb, m = t - q * tb;
+        const uint32_t byte_pos = (NARROW ? 0 : ct * 32) + m;
+        if (q0 + q >= p.q_total || byte_pos >= p.R) continue;
+        uint32_t x = 0;
+        for (int w = 0; w < kWaves; ++w)
+            for (uint32_t b = 0; b < p.bpw; ++b) {
+                const uint32_t c = b * p.lpb + 2 * m;
+                x ^= (uint32_t)nib[w][q][c] | ((uint32_t)nib[w][q][c + 1] << 4);
+            }
+        partials[((uint64_t)group * p.q_total + q0 + q) * p.rpad + byte_pos] = (uint8_t)x;
+    }
+}
+
+// Stage 2: out[q][m] = XOR over groups of partials[g][q][m].  Each workgroup
+// owns `wpb` consecutive 32-bit words of the [q][rpad] result and splits the
+// groups over 256 / wpb slices, then folds the slices through LDS.
+__global__ void __launch_bounds__(kThreads)
+k_stage2(const uint32_t* __restrict__ partials, uint8_t* __restrict__ out, uint32_t groups,
+         uint32_t words, uint32_t wpb, uint32_t rpad, uint32_t R) {
+    __shared__ uint32_t red[kThreads];
+    const uint32_t nsl = kThreads / wpb;
+    const uint32_t wl = threadIdx.x % wpb, sl = threadIdx.x / wpb;
+    const uint32_t w = blockIdx.x * wpb + wl;
+    uint32_t acc = 0;
+    if (w < words && sl < nsl) {
+        uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        uint32_t g = sl;
+        for (; g + 3 * nsl < groups; g += 4 * nsl) {
+            a0 ^= partials[(uint64_t)g * words + w];
+            a1 ^= partials[(uint64_t)(g + nsl) * words + w];
+            a2 ^= partials[(uint64_t)(g + 2 * nsl) * words + w];
+            a3 ^= partials[(uint64_t)(g + 3 * nsl) * words + w];
+        }
+        for (; g < groups; g += nsl) a0 ^= partials[(uint64_t)g * words + w];
+        acc = a0 ^ a1 ^ a2 ^ a3;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (sl == 0 && w < words) {
+        for (uint32_t s = 1; s < nsl; ++s) acc ^= red[s * wpb + wl];
+        const uint32_t q = (4 * w) / rpad, m0 = (4 * w) - q * rpad;
+        for (uint32_t b = 0; b < 4; ++b) {
+            const uint32_t m = m0 + b;
+            if (m < R) out[(uint64_t)q * R + m] = (uint8_t)(acc >> (8 * b));
+        }
+    }
+}
+
+// Natural -> bit-sliced, one wave per 32-record block.  Lanes 0-31 hold byte
+// c of records 0-31 of the block, lanes 32-63 byte c+1; each ballot over bit
+// t yields the two words of columns 8c+t and 8(c+1)+t.
+__global__ void __launch_bounds__(kThreads)
+k_slice(const uint8_t* __restrict__ src, uint64_t nrec, uint32_t R, uint32_t* __restrict__ dst,
+        uint64_t nblk) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t blk = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (blk >= nblk) return;
+    const uint32_t i = lane & 31, h = lane >> 5;
+    const uint64_t rec = blk * 32 + i;
+    const bool valid = rec < nrec;
+    const uint8_t* rp = src + (valid ? rec : 0) * R;
+    uint32_t* out = dst + blk * 8ull * R;
+    for (uint32_t c = 0; c < R; c += 2) {
+        const uint32_t cb = c + h;
+        const uint32_t byte = (valid && cb < R) ? rp[cb] : 0u;
+        uint32_t w = 0;
+#pragma unroll
+        for (uint32_t t = 0; t < 8; ++t) {
+            const unsigned long long m = __ballot((byte >> t) & 1u);
+            if ((lane & 7) == t) w = (lane & 8) ? (uint32_t)(m >> 32) : (uint32_t)m;
+        }
+        const uint32_t col = 8 * c + (lane & 15);
+        if (lane < 16 && col < 8 * R) out[col] = w;
+    }
+}
+
+// Bit-sliced -> natural: lane i < 32 rebuilds record 32*blk + i.
+__global__ void __launch_bounds__(kThreads)
+k_unslice(const uint32_t* __restrict__ src, uint64_t nblk, uint32_t R, uint8_t* __restrict__ dst,
+          uint64_t nrec) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t blk = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (blk >= nblk || lane >= 32) return;
+    const uint64_t rec = blk * 32 + lane;
+    if (rec >= nrec) return;
+    const uint32_t* in = src + blk * 8ull * R;
+    uint8_t* rp = dst + rec * R;
+    for (uint32_t c = 0; c < R; ++c) {
+        uint32_t byte = 0;
+        for (uint32_t t = 0; t < 8; ++t) byte |= ((in[8 * c + t] >> lane) & 1u) << t;
+        rp[c] = (uint8_t)byte;
+    }
+}
+
+template <int QT, int U>
+hipError_t launch_valu_t(const Geometry& g, const Plan& pl, const void* db, const uint32_t* sel,
+                         uint64_t stride_words, uint32_t q, uint8_t* partials, hipStream_t s) {
+    Stage1Params p;
+    p.n_units = g.n_units;
+    p.units_per_group = pl.units_per_group;
+    p.stride_words = stride_words;
+    p.nb = g.nb;
+    p.q_total = q;
+    p.groups = pl.groups;
+    p.n_ct = g.n_ct;
+    p.n_qt = pl.n_qt;
+    p.cpb = g.cpb;
+    p.bpw = g.bpw;
+    p.lpb = g.lpb;
+    p.tile_bytes = g.tile_bytes;
+    p.R = g.R;
+    p.rpad = g.rpad;
+    const uint32_t total = pl.groups * g.n_ct * pl.n_qt;
+    const uint32_t grid = (total + 7) / 8 * 8;
+    if (g.narrow)
+        hipLaunchKernelGGL((k_stage1_valu<QT, U, true>), dim3(grid), dim3(kThreads), 0, s,
+                           (const u32x4*)db, sel, partials, p);
+    else
+        hipLaunchKernelGGL((k_stage1_valu<QT, U, false>), dim3(grid), dim3(kThreads), 0, s,
+                           (const u32x4*)db, sel, partials, p);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// (QT, U) pairs compiled for the vector-ALU scan.
+#define PIR_VALU_TABLE(X) \
+    X(1, 4) X(1, 8) X(1, 16) \
+    X(2, 4) X(2, 8) \
+    X(4, 2) X(4, 4) X(4, 8) \
+    X(8, 1) X(8, 2) X(8, 4) \
+    X(16, 1) X(16, 2) X(16, 4) \
+    X(32, 1) X(32, 2)
+
+bool valu_supported(uint32_t qt, uint32_t unroll) {
+#define X(a, b) if (qt == a && unroll == b) return true;
+    PIR_VALU_TABLE(X)
+#undef X
+    return false;
+}
+
+hipError_t launch_stage1_valu(const Geometry& g, const Plan& p, const void* db, const uint32_t* sel,
+                              uint64_t stride_words, uint32_t q, uint8_t* partials, hipStream_t s) {
+#define X(a, b) \
+    if (p.qt == a && p.unroll == b) return launch_valu_t<a, b>(g, p, db, sel, stride_words, q, partials, s);
+    PIR_VALU_TABLE(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_stage2(const Geometry& g, uint32_t groups, uint32_t q, const uint8_t* partials,
+                         uint8_t* out, hipStream_t s) {
+    const uint32_t words = q * (g.rpad / 4);
+    const uint32_t wpb = words < 16 ? words : 16;
+    const uint32_t grid = (words + wpb - 1) / wpb;
+    hipLaunchKernelGGL(k_stage2, dim3(grid), dim3(kThreads), 0, s, (const uint32_t*)partials, out,
+                       groups, words, wpb, g.rpad, g.R);
+    return hipGetLastError();
+}
+
+hipError_t launch_slice(const Geometry& g, const uint8_t* src, uint64_t nrec, uint32_t* dst_block0,
+                        uint64_t nblk, hipStream_t s) {
+    if (nblk == 0) return hipSuccess;
+    const uint64_t grid = (nblk + kWaves - 1) / kWaves;
+    hipLaunchKernelGGL(k_slice, dim3((uint32_t)grid), dim3(kThreads), 0, s, src, nrec, g.R,
+                       dst_block0, nblk);
+    return hipGetLastError();
+}
+
+hipError_t launch_unslice(const Geometry& g, const uint32_t* src_block0, uint64_t nblk, uint8_t* dst,
+                          uint64_t nrec, hipStream_t s) {
+    if (nblk == 0) return hipSuccess;
+    const uint64_t grid = (nblk + kWaves - 1) / kWaves;
+    hipLaunchKernelGGL(k_unslice, dim3((uint32_t)grid), dim3(kThreads), 0, s, src_block0, nblk, g.R,
+                       dst, nrec);
+    return hipGetLastError();
+}
+
+bool mfma_supported(uint32_t, const Geometry&, uint32_t, uint32_t) { return false; }
+
+hipError_t launch_stage1_mfma(const Geometry&, const Plan&, const void*, const uint32_t*, uint64_t,
+                              uint32_t, uint8_t*, hipStream_t) {
+    return hipErrorNotSupported;
+}
+
+Geometry make_geometry(uint64_t n, uint32_t R) {
+    Geometry g;
+    g.n = n;
+    g.R = R;
+    g.rpad = (R + 3) / 4 * 4;
+    g.nb = (n + 31) / 32;
+    g.cpb = 2 * R;
+    g.narrow = R < 32;
+    if (g.narrow) {
+        g.lpb = g.cpb;
+        g.bpw = 64 / g.cpb;
+        g.n_ct = 1;
+        g.tile_bytes = R;
+    } else {
+        g.lpb = 64;
+        g.bpw = 1;
+        g.n_ct = (g.cpb + 63) / 64;
+        g.tile_bytes = 32;
+    }
+    g.n_units = (g.nb + g.bpw - 1) / g.bpw;
+    g.nb_alloc = g.n_units * g.bpw;
+    return g;
+}
+
+}  // namespace pir

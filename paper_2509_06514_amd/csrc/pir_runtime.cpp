@@ -1,0 +1,773 @@
+// Host runtime behind the C ABI: device context, resident databases, pooled
+// execution slots for the synchronous calls, per-stream scratch workspaces,
+// kernel timing and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "pir_internal.h"
+#include "pir_runtime.h"
+
+namespace pir {
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(e == hipErrorOutOfMemory ? PIR_E_NOMEM : PIR_E_DEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+void clear_error() { g_last_error.clear(); }
+
+// ------------------------------------------------------------------ buffers
+
+DevBuf::~DevBuf() { reset(); }
+void DevBuf::reset() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+hipError_t DevBuf::ensure(size_t want) {
+    if (want <= bytes) return hipSuccess;
+    reset();
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) return e;
+    ptr = p;
+    bytes = want;
+    return hipSuccess;
+}
+
+HostBuf::~HostBuf() { reset(); }
+void HostBuf::reset() {
+    if (ptr) (void)hipHostFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+hipError_t HostBuf::ensure(size_t want) {
+    if (want <= bytes) return hipSuccess;
+    reset();
+    void* p = nullptr;
+    hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    ptr = p;
+    bytes = want;
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------------ planning
+
+static uint32_t pow2_ceil(uint32_t x) {
+    uint32_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+static uint32_t default_unroll(uint32_t qt) {
+    if (qt == 1) return 8;
+    if (qt <= 2) return 4;
+    if (qt <= 4) return 4;
+    if (qt <= 16) return 2;
+    return 1;
+}
+
+// Fill the derived fields of a plan (tiles, groups, grid) for q queries.
+int finish_plan(const Geometry& g, uint32_t q, Plan& p) {
+    if (p.variant == PIR_VARIANT_AUTO) p.variant = PIR_VARIANT_VALU;
+    if (p.variant == PIR_VARIANT_VALU) {
+        if (p.qt == 0) p.qt = std::min<uint32_t>(16, pow2_ceil(q));
+        if (p.unroll == 0) p.unroll = default_unroll(p.qt);
+        if (!valu_supported(p.qt, p.unroll))
+            return fail(PIR_E_INVAL, "no VALU kernel for q_tile=%u unroll=%u", p.qt, p.unroll);
+    } else if (p.variant == PIR_VARIANT_MFMA_I8 || p.variant == PIR_VARIANT_MFMA_F4) {
+        if (p.qt == 0) p.qt = 64;
+        if (p.unroll == 0) p.unroll = 1;
+        if (!mfma_supported(p.variant, g, p.qt, p.unroll))
+            return fail(PIR_E_INVAL, "no MFMA kernel (variant %u) for R=%u q_tile=%u unroll=%u",
+                        p.variant, g.R, p.qt, p.unroll);
+    } else {
+        return fail(PIR_E_INVAL, "unknown kernel variant %u", p.variant);
+    }
+    p.n_qt = (q + p.qt - 1) / p.qt;
+    const uint64_t co = (uint64_t)g.n_ct * p.n_qt;
+    // smallest slice of units worth a workgroup: one full iteration of its 4 waves
+    const uint64_t min_units = 4ull * p.unroll;
+    uint64_t groups = p.groups;
+    if (groups == 0) {
+        const uint64_t target_wg = 2048;  // 256 CUs x 8 resident workgroups
+        groups = std::max<uint64_t>(1, target_wg / co);
+    }
+    groups = std::min<uint64_t>(groups, std::max<uint64_t>(1, (g.n_units + min_units - 1) / min_units));
+    uint64_t upg = (g.n_units + groups - 1) / groups;
+    upg = (upg + min_units - 1) / min_units * min_units;
+    groups = (g.n_units + upg - 1) / upg;
+    if (groups * co > (1ull << 31)) return fail(PIR_E_INVAL, "grid too large");
+    p.groups = (uint32_t)groups;
+    p.units_per_group = upg;
+    const uint64_t total = groups * co;
+    p.grid = (uint32_t)((total + 7) / 8 * 8);
+    return PIR_OK;
+}
+
+size_t partial_bytes(const Geometry& g, const Plan& p, uint32_t q) {
+    return (size_t)p.groups * q * g.rpad;
+}
+
+// ------------------------------------------------------------------ context
+
+Ctx::~Ctx() {
+    (void)hipSetDevice(device);
+    for (auto& e : pool) {
+        if (e->stream) (void)hipStreamDestroy(e->stream);
+    }
+    pool.clear();
+    for (auto& kv : workspaces) kv.second.reset();
+    std::vector<hipEvent_t> evs(free_events);
+    for (auto& t : pending) {
+        evs.push_back(t.a);
+        evs.push_back(t.b);
+    }
+    std::sort(evs.begin(), evs.end());
+    evs.erase(std::unique(evs.begin(), evs.end()), evs.end());
+    for (auto ev : evs) (void)hipEventDestroy(ev);
+}
+
+int Ctx::bind() {
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    return PIR_OK;
+}
+
+int Ctx::acquire(Exec** out) {
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto& e : pool)
+        if (!e->busy) {
+            e->busy = true;
+            *out = e.get();
+            return PIR_OK;
+        }
+    auto e = std::make_unique<Exec>();
+    hipError_t he = hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking);
+    if (he != hipSuccess) return hip_fail(he, "hipStreamCreate");
+    e->busy = true;
+    *out = e.get();
+    pool.push_back(std::move(e));
+    return PIR_OK;
+}
+
+void Ctx::release(Exec* e) {
+    std::lock_guard<std::mutex> lk(mu);
+    e->busy = false;
+}
+
+hipEvent_t Ctx::take_event() {
+    if (!free_events.empty()) {
+        hipEvent_t ev = free_events.back();
+        free_events.pop_back();
+        return ev;
+    }
+    hipEvent_t ev = nullptr;
+    if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+    return ev;
+}
+
+// Enqueue stage 1 + stage 2 for q queries on `s` with scratch `partials`.
+int Ctx::enqueue_scan(const Db& db, const Plan& p, const uint32_t* d_sel, uint64_t stride_words,
+                      uint32_t q, uint8_t* d_out, uint8_t* partials, hipStream_t s) {
+    const bool timed = timing_on.load();
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+    if (timed) {
+        std::lock_guard<std::mutex> lk(mu);
+        e0 = take_event();
+        e1 = take_event();
+        e2 = take_event();
+    }
+    if (e0) (void)hipEventRecord(e0, s);
+    hipError_t he;
+    if (p.variant == PIR_VARIANT_VALU)
+        he = launch_stage1_valu(db.geo, p, db.data.ptr, d_sel, stride_words, q, partials, s);
+    else
+        he = launch_stage1_mfma(db.geo, p, db.data.ptr, d_sel, stride_words, q, partials, s);
+    if (he != hipSuccess) return hip_fail(he, "stage-1 launch");
+    if (e1) (void)hipEventRecord(e1, s);
+    he = launch_stage2(db.geo, p.groups, q, partials, d_out, s);
+    if (he != hipSuccess) return hip_fail(he, "stage-2 launch");
+    if (e2) (void)hipEventRecord(e2, s);
+    if (timed && e0 && e1 && e2) {
+        // stage 1 = (e0, e1), stage 2 = (e1, e2); pir_timing_read frees each event once
+        std::lock_guard<std::mutex> lk(mu);
+        pending.push_back({e0, e1, 1});
+        pending.push_back({e1, e2, 2});
+    }
+    return PIR_OK;
+}
+
+int Ctx::plan_for(const Db& db, uint32_t q, const pir_kernel_cfg* cfg, Plan& p) {
+    Plan base;
+    if (cfg && cfg->variant != PIR_VARIANT_AUTO) {
+        base.variant = cfg->variant;
+        base.qt = cfg->q_tile;
+        base.unroll = cfg->unroll;
+        base.groups = cfg->groups;
+    } else {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = tuned.find(tune_key(db.geo, q));
+        if (it != tuned.end()) {
+            base.variant = it->second.variant;
+            base.qt = it->second.q_tile;
+            base.unroll = it->second.unroll;
+            base.groups = it->second.groups;
+        } else {
+            base.variant = PIR_VARIANT_VALU;
+        }
+    }
+    p = base;
+    return finish_plan(db.geo, q, p);
+}
+
+std::string Ctx::tune_key(const Geometry& g, uint32_t q) const {
+    uint32_t nbits = 0;
+    while ((1ull << (nbits + 1)) <= g.nb) ++nbits;
+    std::ostringstream os;
+    os << arch << "/R" << g.R << "/Q" << pow2_ceil(q) << "/NB" << nbits;
+    return os.str();
+}
+
+void Ctx::save_tune_cache() {
+    const char* path = std::getenv("PIR_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::ofstream f(path);
+    if (!f) return;
+    f << "{\n";
+    bool first = true;
+    for (auto& kv : tuned) {
+        if (!first) f << ",\n";
+        first = false;
+        f << "  \"" << kv.first << "\": {\"variant\": " << kv.second.variant
+          << ", \"q_tile\": " << kv.second.q_tile << ", \"unroll\": " << kv.second.unroll
+          << ", \"groups\": " << kv.second.groups << "}";
+    }
+    f << "\n}\n";
+}
+
+void Ctx::load_tune_cache() {
+    const char* path = std::getenv("PIR_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::ifstream f(path);
+    if (!f) return;
+    std::string line;
+    while (std::getline(f, line)) {
+        // "key": {"variant": V, "q_tile": T, "unroll": U, "groups": G}
+        size_t a = line.find('"');
+        if (a == std::string::npos) continue;
+        size_t b = line.find('"', a + 1);
+        if (b == std::string::npos) continue;
+        std::string key = line.substr(a + 1, b - a - 1);
+        pir_kernel_cfg c{};
+        if (sscanf(line.c_str() + b + 1, ": {\"variant\": %u, \"q_tile\": %u, \"unroll\": %u, \"groups\": %u",
+                   &c.variant, &c.q_tile, &c.unroll, &c.groups) == 4)
+            tuned[key] = c;
+    }
+}
+
+}  // namespace pir
+
+using namespace pir;
+
+// ======================================================================= ABI
+
+extern "C" {
+
+const char* pir_last_error(void) { return g_last_error.c_str(); }
+
+const char* pir_version(void) { return "pir-mi355x 0.1 (gfx950)"; }
+
+int pir_ctx_create(int hip_device, pir_ctx** out) {
+    clear_error();
+    if (!out) return fail(PIR_E_INVAL, "pir_ctx_create: out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev == 0) return fail(PIR_E_DEVICE, "no HIP device available");
+    if (hip_device < 0 || hip_device >= ndev)
+        return fail(PIR_E_INVAL, "device %d out of range (%d devices)", hip_device, ndev);
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, hip_device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    std::string arch = prop.gcnArchName;
+    if (arch.rfind("gfx950", 0) != 0)
+        return fail(PIR_E_DEVICE, "device %d is %s; this library is built for gfx950 only", hip_device,
+                    arch.c_str());
+    auto ctx = std::make_unique<Ctx>();
+    ctx->device = hip_device;
+    ctx->arch = "gfx950";
+    ctx->n_cu = prop.multiProcessorCount;
+    int rc = ctx->bind();
+    if (rc) return rc;
+    ctx->load_tune_cache();
+    *out = reinterpret_cast<pir_ctx*>(ctx.release());
+    return PIR_OK;
+}
+
+int pir_ctx_destroy(pir_ctx* c) {
+    clear_error();
+    if (!c) return fail(PIR_E_INVAL, "pir_ctx_destroy: NULL");
+    Ctx* ctx = reinterpret_cast<Ctx*>(c);
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    delete ctx;
+    return PIR_OK;
+}
+
+// Upload row-major records [first, first + count) (host) into the bit-sliced
+// device copy.  Whole blocks are rewritten: a block only partly covered is
+// first read back (unsliced) so its other records survive.
+static int write_records(Db* db, uint64_t first, uint64_t count, const uint8_t* host) {
+    Ctx* ctx = db->ctx;
+    const Geometry& g = db->geo;
+    const uint32_t R = g.R;
+    hipStream_t s = db->ctx_stream;
+    const uint64_t blk_lo = first / 32, blk_hi = (first + count + 31) / 32;  // [lo, hi)
+    // staging chunk: at most 2^22 records (e.g. 128 MiB at R = 32)
+    const uint64_t max_blocks = std::max<uint64_t>(1, (256ull << 20) / (32ull * R));
+    DevBuf stage;
+    hipError_t e = stage.ensure(std::min<uint64_t>(blk_hi - blk_lo, max_blocks) * 32ull * R);
+    if (e != hipSuccess) return hip_fail(e, "staging allocation");
+    for (uint64_t b0 = blk_lo; b0 < blk_hi; b0 += max_blocks) {
+        const uint64_t nblk = std::min(max_blocks, blk_hi - b0);
+        const uint64_t r0 = b0 * 32, r1 = std::min<uint64_t>((b0 + nblk) * 32, g.n);
+        // records of this chunk that come from the host buffer
+        const uint64_t h0 = std::max(r0, first), h1 = std::min(r1, first + count);
+        uint8_t* st = (uint8_t*)stage.ptr;
+        uint32_t* dst = (uint32_t*)db->data.ptr + b0 * 8ull * R;
+        if (h0 > r0 || h1 < r1) {
+            e = launch_unslice(g, dst, nblk, st, r1 - r0, s);
+            if (e != hipSuccess) return hip_fail(e, "unslice launch");
+        }
+        e = hipMemcpyAsync(st + (h0 - r0) * R, host + (h0 - first) * R, (h1 - h0) * R,
+                           hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "record upload");
+        e = launch_slice(g, st, r1 - r0, dst, nblk, s);
+        if (e != hipSuccess) return hip_fail(e, "slice launch");
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "record upload sync");
+    }
+    return PIR_OK;
+}
+
+int pir_db_load(pir_ctx* c, const void* records, uint64_t n_records, uint32_t record_bytes,
+                pir_db** out) {
+    clear_error();
+    if (!c || !records || !out) return fail(PIR_E_INVAL, "pir_db_load: NULL argument");
+    *out = nullptr;
+    if (n_records == 0 || record_bytes == 0)
+        return fail(PIR_E_INVAL, "pir_db_load: N and R must be positive");
+    if (record_bytes > (1u << 20)) return fail(PIR_E_INVAL, "pir_db_load: R > 1 MiB");
+    if (n_records > (1ull << 40) || n_records > UINT64_MAX / record_bytes)
+        return fail(PIR_E_INVAL, "pir_db_load: N*R overflows");
+    Ctx* ctx = reinterpret_cast<Ctx*>(c);
+    int rc = ctx->bind();
+    if (rc) return rc;
+    auto db = std::make_unique<Db>();
+    db->ctx = ctx;
+    db->geo = make_geometry(n_records, record_bytes);
+    hipError_t e = hipStreamCreateWithFlags(&db->ctx_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    e = db->data.ensure(db->geo.bytes());
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(db->ctx_stream);
+        return fail(PIR_E_NOMEM, "pir_db_load: cannot allocate %llu bytes of HBM",
+                    (unsigned long long)db->geo.bytes());
+    }
+    // padding blocks past the last record must read as zero records
+    const uint64_t used = ((n_records + 31) / 32) * 32ull * record_bytes;
+    if (db->geo.bytes() > used) {
+        e = hipMemsetAsync((uint8_t*)db->data.ptr + used, 0, db->geo.bytes() - used, db->ctx_stream);
+        if (e != hipSuccess) {
+            (void)hipStreamDestroy(db->ctx_stream);
+            return hip_fail(e, "padding clear");
+        }
+    }
+    rc = write_records(db.get(), 0, n_records, (const uint8_t*)records);
+    if (rc) {
+        db->data.reset();
+        (void)hipStreamDestroy(db->ctx_stream);
+        return rc;
+    }
+    *out = reinterpret_cast<pir_db*>(db.release());
+    return PIR_OK;
+}
+
+int pir_db_update(pir_db* d, uint64_t first, uint64_t count, const void* records) {
+    clear_error();
+    if (!d || !records) return fail(PIR_E_INVAL, "pir_db_update: NULL argument");
+    Db* db = reinterpret_cast<Db*>(d);
+    if (count == 0) return PIR_OK;
+    if (first >= db->geo.n || count > db->geo.n - first)
+        return fail(PIR_E_INVAL, "pir_db_update: range [%llu, +%llu) outside N=%llu",
+                    (unsigned long long)first, (unsigned long long)count,
+                    (unsigned long long)db->geo.n);
+    int rc = db->ctx->bind();
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(db->mu);
+    return write_records(db, first, count, (const uint8_t*)records);
+}
+
+int pir_db_read(pir_db* d, uint64_t first, uint64_t count, void* out_records) {
+    clear_error();
+    if (!d || !out_records) return fail(PIR_E_INVAL, "pir_db_read: NULL argument");
+    Db* db = reinterpret_cast<Db*>(d);
+    const Geometry& g = db->geo;
+    if (count == 0) return PIR_OK;
+    if (first >= g.n || count > g.n - first) return fail(PIR_E_INVAL, "pir_db_read: range outside N");
+    int rc = db->ctx->bind();
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(db->mu);
+    const uint64_t blk_lo = first / 32, blk_hi = (first + count + 31) / 32;
+    const uint64_t max_blocks = std::max<uint64_t>(1, (256ull << 20) / (32ull * g.R));
+    DevBuf stage;
+    hipError_t e = stage.ensure(std::min<uint64_t>(blk_hi - blk_lo, max_blocks) * 32ull * g.R);
+    if (e != hipSuccess) return hip_fail(e, "staging allocation");
+    for (uint64_t b0 = blk_lo; b0 < blk_hi; b0 += max_blocks) {
+        const uint64_t nblk = std::min(max_blocks, blk_hi - b0);
+        const uint64_t r0 = b0 * 32, r1 = std::min<uint64_t>((b0 + nblk) * 32, g.n);
+        const uint64_t h0 = std::max(r0, first), h1 = std::min(r1, first + count);
+        e = launch_unslice(g, (const uint32_t*)db->data.ptr + b0 * 8ull * g.R, nblk,
+                           (uint8_t*)stage.ptr, r1 - r0, db->ctx_stream);
+        if (e != hipSuccess) return hip_fail(e, "unslice launch");
+        e = hipMemcpyAsync((uint8_t*)out_records + (h0 - first) * g.R,
+                           (uint8_t*)stage.ptr + (h0 - r0) * g.R, (h1 - h0) * g.R,
+                           hipMemcpyDeviceToHost, db->ctx_stream);
+        if (e != hipSuccess) return hip_fail(e, "record download");
+        e = hipStreamSynchronize(db->ctx_stream);
+        if (e != hipSuccess) return hip_fail(e, "record download sync");
+    }
+    return PIR_OK;
+}
+
+int pir_db_free(pir_db* d) {
+    clear_error();
+    if (!d) return fail(PIR_E_INVAL, "pir_db_free: NULL");
+    Db* db = reinterpret_cast<Db*>(d);
+    (void)db->ctx->bind();
+    (void)hipDeviceSynchronize();
+    db->data.reset();
+    if (db->ctx_stream) (void)hipStreamDestroy(db->ctx_stream);
+    delete db;
+    return PIR_OK;
+}
+
+int pir_db_get_info(const pir_db* d, pir_db_info* out) {
+    clear_error();
+    if (!d || !out) return fail(PIR_E_INVAL, "pir_db_get_info: NULL argument");
+    const Db* db = reinterpret_cast<const Db*>(d);
+    out->n_records = db->geo.n;
+    out->record_bytes = db->geo.R;
+    out->reserved = 0;
+    out->n_blocks = db->geo.nb;
+    out->device_bytes = db->geo.bytes();
+    out->sel_words = db->geo.nb;
+    return PIR_OK;
+}
+
+uint64_t pir_db_min_sel_stride(const pir_db* d) {
+    if (!d) return 0;
+    return 4ull * reinterpret_cast<const Db*>(d)->geo.nb;
+}
+
+static int check_async_args(Db* db, const void* d_sel, uint64_t sel_stride, uint32_t q, void* d_out) {
+    if (!db || !d_sel || !d_out) return fail(PIR_E_INVAL, "NULL argument");
+    if (q == 0 || q > PIR_MAX_BATCH) return fail(PIR_E_INVAL, "q=%u outside [1, %u]", q, PIR_MAX_BATCH);
+    if (sel_stride % 4 != 0 || sel_stride < 4ull * db->geo.nb)
+        return fail(PIR_E_INVAL, "sel_stride %llu must be a multiple of 4 and >= %llu",
+                    (unsigned long long)sel_stride, (unsigned long long)(4ull * db->geo.nb));
+    if (((uintptr_t)d_sel) % 4 != 0) return fail(PIR_E_INVAL, "d_sel must be 4-byte aligned");
+    return PIR_OK;
+}
+
+int pir_dpxor_batch_async_cfg(pir_db* d, const void* d_sel, uint64_t sel_stride, uint32_t q, void* d_out,
+                              void* hip_stream, const pir_kernel_cfg* cfg) {
+    clear_error();
+    Db* db = reinterpret_cast<Db*>(d);
+    int rc = check_async_args(db, d_sel, sel_stride, q, d_out);
+    if (rc) return rc;
+    Ctx* ctx = db->ctx;
+    rc = ctx->bind();
+    if (rc) return rc;
+    Plan p;
+    rc = ctx->plan_for(*db, q, cfg, p);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    uint8_t* partials = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        DevBuf& ws = ctx->workspaces[s];
+        const size_t need = partial_bytes(db->geo, p, q);
+        if (need > ws.bytes) {
+            if (ws.ptr) {
+                hipError_t e = hipStreamSynchronize(s);
+                if (e != hipSuccess) return hip_fail(e, "workspace sync");
+            }
+            hipError_t e = ws.ensure(need + need / 4);
+            if (e != hipSuccess) return hip_fail(e, "workspace allocation");
+        }
+        partials = (uint8_t*)ws.ptr;
+    }
+    return ctx->enqueue_scan(*db, p, (const uint32_t*)d_sel, sel_stride / 4, q, (uint8_t*)d_out, partials, s);
+}
+
+int pir_dpxor_batch_async(pir_db* d, const void* d_sel, uint64_t sel_stride, uint32_t q, void* d_out,
+                          void* hip_stream) {
+    return pir_dpxor_batch_async_cfg(d, d_sel, sel_stride, q, d_out, hip_stream, nullptr);
+}
+
+// Synchronous path: pack host rows into pinned staging, upload, scan, download.
+int pir_dpxor_batch(pir_db* d, const uint8_t* sel_bits, uint64_t sel_stride, uint32_t q, uint8_t* out) {
+    clear_error();
+    Db* db = reinterpret_cast<Db*>(d);
+    if (!db || !sel_bits || !out) return fail(PIR_E_INVAL, "pir_dpxor_batch: NULL argument");
+    if (q == 0 || q > PIR_MAX_BATCH) return fail(PIR_E_INVAL, "q=%u outside [1, %u]", q, PIR_MAX_BATCH);
+    const Geometry& g = db->geo;
+    const uint64_t row_bytes = (g.n + 7) / 8;
+    if (sel_stride < row_bytes)
+        return fail(PIR_E_INVAL, "sel_stride %llu < ceil(N/8) = %llu", (unsigned long long)sel_stride,
+                    (unsigned long long)row_bytes);
+    Ctx* ctx = db->ctx;
+    int rc = ctx->bind();
+    if (rc) return rc;
+    Plan p;
+    rc = ctx->plan_for(*db, q, nullptr, p);
+    if (rc) return rc;
+    Exec* ex = nullptr;
+    rc = ctx->acquire(&ex);
+    if (rc) return rc;
+    struct Releaser {
+        Ctx* c;
+        Exec* e;
+        ~Releaser() { c->release(e); }
+    } rel{ctx, ex};
+    const uint64_t dstride = (4ull * g.nb + 255) / 256 * 256;  // device row pitch
+    const size_t sel_bytes = (size_t)dstride * q, out_bytes = (size_t)g.R * q;
+    hipError_t e;
+    if ((e = ex->h_sel.ensure(sel_bytes)) != hipSuccess) return hip_fail(e, "pinned selection staging");
+    if ((e = ex->d_sel.ensure(sel_bytes)) != hipSuccess) return hip_fail(e, "device selection buffer");
+    if ((e = ex->h_out.ensure(out_bytes)) != hipSuccess) return hip_fail(e, "pinned answer staging");
+    if ((e = ex->d_out.ensure(out_bytes)) != hipSuccess) return hip_fail(e, "device answer buffer");
+    if ((e = ex->partials.ensure(partial_bytes(g, p, q))) != hipSuccess) return hip_fail(e, "workspace");
+    uint8_t* hs = (uint8_t*)ex->h_sel.ptr;
+    for (uint32_t i = 0; i < q; ++i) {
+        uint8_t* row = hs + (size_t)i * dstride;
+        memcpy(row, sel_bits + (size_t)i * sel_stride, row_bytes);
+        memset(row + row_bytes, 0, dstride - row_bytes);
+    }
+    if ((e = hipMemcpyAsync(ex->d_sel.ptr, hs, sel_bytes, hipMemcpyHostToDevice, ex->stream)) != hipSuccess)
+        return hip_fail(e, "selection upload");
+    rc = ctx->enqueue_scan(*db, p, (const uint32_t*)ex->d_sel.ptr, dstride / 4, q, (uint8_t*)ex->d_out.ptr,
+                           (uint8_t*)ex->partials.ptr, ex->stream);
+    if (rc) return rc;
+    if ((e = hipMemcpyAsync(ex->h_out.ptr, ex->d_out.ptr, out_bytes, hipMemcpyDeviceToHost, ex->stream)) !=
+        hipSuccess)
+        return hip_fail(e, "answer download");
+    if ((e = hipStreamSynchronize(ex->stream)) != hipSuccess) return hip_fail(e, "scan");
+    memcpy(out, ex->h_out.ptr, out_bytes);
+    return PIR_OK;
+}
+
+int pir_dpxor(pir_db* d, const uint8_t* sel_bits, uint8_t* out_record) {
+    Db* db = reinterpret_cast<Db*>(d);
+    if (!db) {
+        clear_error();
+        return fail(PIR_E_INVAL, "pir_dpxor: NULL database");
+    }
+    return pir_dpxor_batch(d, sel_bits, (db->geo.n + 7) / 8, 1, out_record);
+}
+
+int pir_get_cfg(pir_db* d, uint32_t q, pir_kernel_cfg* out) {
+    clear_error();
+    Db* db = reinterpret_cast<Db*>(d);
+    if (!db || !out) return fail(PIR_E_INVAL, "pir_get_cfg: NULL argument");
+    if (q == 0 || q > PIR_MAX_BATCH) return fail(PIR_E_INVAL, "q out of range");
+    Plan p;
+    int rc = db->ctx->plan_for(*db, q, nullptr, p);
+    if (rc) return rc;
+    out->variant = p.variant;
+    out->q_tile = p.qt;
+    out->unroll = p.unroll;
+    out->groups = p.groups;
+    return PIR_OK;
+}
+
+int pir_tune(pir_db* d, uint32_t q, pir_kernel_cfg* out) {
+    clear_error();
+    Db* db = reinterpret_cast<Db*>(d);
+    if (!db) return fail(PIR_E_INVAL, "pir_tune: NULL database");
+    if (q == 0 || q > PIR_MAX_BATCH) return fail(PIR_E_INVAL, "q out of range");
+    Ctx* ctx = db->ctx;
+    int rc = ctx->bind();
+    if (rc) return rc;
+    const Geometry& g = db->geo;
+    // candidates
+    std::vector<pir_kernel_cfg> cands;
+    const uint32_t qts[] = {1, 2, 4, 8, 16, 32};
+    const uint32_t unrolls[] = {1, 2, 4, 8, 16};
+    for (uint32_t qt : qts) {
+        if (qt > pow2_ceil(q) || (qt > 1 && qt > q && qt / 2 >= q)) continue;
+        for (uint32_t u : unrolls)
+            if (valu_supported(qt, u)) cands.push_back({PIR_VARIANT_VALU, qt, u, 0});
+    }
+    for (uint32_t v : {PIR_VARIANT_MFMA_I8, PIR_VARIANT_MFMA_F4})
+        for (uint32_t qt : {16u, 32u, 64u})
+            for (uint32_t u : {1u, 2u})
+                if (q >= 8 && mfma_supported(v, g, qt, u)) cands.push_back({v, qt, u, 0});
+    // grid variants of each
+    std::vector<pir_kernel_cfg> all;
+    for (auto c : cands) {
+        Plan p;
+        p.variant = c.variant;
+        p.qt = c.q_tile;
+        p.unroll = c.unroll;
+        if (finish_plan(g, q, p)) continue;
+        for (uint32_t mult : {1u, 2u}) {
+            pir_kernel_cfg cc = c;
+            cc.groups = std::max<uint32_t>(1, p.groups * mult / 2);
+            all.push_back(cc);
+            cc.groups = p.groups * mult;
+            all.push_back(cc);
+        }
+    }
+    if (all.empty()) return fail(PIR_E_INVAL, "pir_tune: no candidate kernels");
+    // scratch selections (content does not affect timing: the scan is oblivious)
+    const uint64_t stride = 4ull * g.nb;
+    DevBuf sel, outb;
+    hipError_t e;
+    if ((e = sel.ensure(stride * q)) != hipSuccess) return hip_fail(e, "tune selections");
+    if ((e = outb.ensure((size_t)g.R * q)) != hipSuccess) return hip_fail(e, "tune output");
+    hipStream_t s = db->ctx_stream;
+    if ((e = hipMemsetAsync(sel.ptr, 0x5A, stride * q, s)) != hipSuccess) return hip_fail(e, "tune memset");
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+        return fail(PIR_E_DEVICE, "event create");
+    float best = 1e30f;
+    pir_kernel_cfg best_cfg{};
+    DevBuf ws;
+    const bool was_timing = ctx->timing_on.exchange(false);
+    for (auto& c : all) {
+        Plan p;
+        p.variant = c.variant;
+        p.qt = c.q_tile;
+        p.unroll = c.unroll;
+        p.groups = c.groups;
+        if (finish_plan(g, q, p)) continue;
+        if ((e = ws.ensure(partial_bytes(g, p, q))) != hipSuccess) continue;
+        rc = ctx->enqueue_scan(*db, p, (const uint32_t*)sel.ptr, stride / 4, q, (uint8_t*)outb.ptr,
+                               (uint8_t*)ws.ptr, s);
+        if (rc) continue;
+        const int reps = 3;
+        (void)hipEventRecord(a, s);
+        for (int i = 0; i < reps; ++i)
+            (void)ctx->enqueue_scan(*db, p, (const uint32_t*)sel.ptr, stride / 4, q, (uint8_t*)outb.ptr,
+                                    (uint8_t*)ws.ptr, s);
+        (void)hipEventRecord(b, s);
+        if (hipEventSynchronize(b) != hipSuccess) break;
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, a, b);
+        ms /= reps;
+        if (ms < best) {
+            best = ms;
+            best_cfg = c;
+            best_cfg.groups = p.groups;
+        }
+    }
+    ctx->timing_on.store(was_timing);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipStreamSynchronize(s);
+    if (best >= 1e30f) return fail(PIR_E_DEVICE, "pir_tune: every candidate failed");
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->tuned[ctx->tune_key(g, q)] = best_cfg;
+        ctx->save_tune_cache();
+    }
+    if (out) *out = best_cfg;
+    return PIR_OK;
+}
+
+int pir_timing_enable(pir_ctx* c, int on) {
+    clear_error();
+    if (!c) return fail(PIR_E_INVAL, "NULL context");
+    reinterpret_cast<Ctx*>(c)->timing_on.store(on != 0);
+    return PIR_OK;
+}
+
+int pir_timing_read(pir_ctx* c, pir_timing* out, int reset) {
+    clear_error();
+    if (!c || !out) return fail(PIR_E_INVAL, "NULL argument");
+    Ctx* ctx = reinterpret_cast<Ctx*>(c);
+    int rc = ctx->bind();
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (auto& t : ctx->pending) {
+        hipError_t e = hipEventSynchronize(t.b);
+        if (e != hipSuccess) return hip_fail(e, "timing event");
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, t.a, t.b);
+        if (t.stage == 1) {
+            ctx->acc.stage1_launches++;
+            ctx->acc.stage1_ms += ms;
+        } else {
+            ctx->acc.stage2_launches++;
+            ctx->acc.stage2_ms += ms;
+        }
+    }
+    // e1 appears in two records (end of stage 1, start of stage 2): free each event once
+    std::vector<hipEvent_t> evs;
+    for (auto& t : ctx->pending) {
+        evs.push_back(t.a);
+        evs.push_back(t.b);
+    }
+    std::sort(evs.begin(), evs.end());
+    evs.erase(std::unique(evs.begin(), evs.end()), evs.end());
+    for (auto ev : evs) ctx->free_events.push_back(ev);
+    ctx->pending.clear();
+    *out = ctx->acc;
+    if (reset) ctx->acc = pir_timing{};
+    return PIR_OK;
+}
+
+void* pir_host_alloc(size_t bytes) {
+    void* p = nullptr;
+    if (bytes == 0) return nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+    return p;
+}
+
+void pir_host_free(void* p) {
+    if (p) (void)hipHostFree(p);
+}
+
+}  // extern "C"

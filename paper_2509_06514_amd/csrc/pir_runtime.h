@@ -1,0 +1,99 @@
+// Runtime objects behind the opaque C handles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "pir_internal.h"
+
+namespace pir {
+
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+void clear_error();
+
+// Growable device buffer (contents are not preserved on growth).
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf();
+    void reset();
+    hipError_t ensure(size_t want);
+};
+
+// Growable pinned host buffer.
+struct HostBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    HostBuf() = default;
+    HostBuf(const HostBuf&) = delete;
+    HostBuf& operator=(const HostBuf&) = delete;
+    ~HostBuf();
+    void reset();
+    hipError_t ensure(size_t want);
+};
+
+// Execution slot for the synchronous calls: a stream with its own staging
+// and scratch buffers.
+struct Exec {
+    hipStream_t stream = nullptr;
+    bool busy = false;
+    HostBuf h_sel, h_out;
+    DevBuf d_sel, d_out, partials;
+};
+
+struct TimedPair {
+    hipEvent_t a, b;
+    int stage;
+};
+
+struct Ctx;
+
+struct Db {
+    Ctx* ctx = nullptr;
+    Geometry geo;
+    DevBuf data;                    // bit-sliced records
+    hipStream_t ctx_stream = nullptr;  // load / update / tuning
+    std::mutex mu;                  // serialises updates and reads
+};
+
+struct Ctx {
+    int device = 0;
+    std::string arch;
+    int n_cu = 0;
+    std::mutex mu;
+    std::vector<std::unique_ptr<Exec>> pool;
+    std::unordered_map<hipStream_t, DevBuf> workspaces;  // per caller stream
+    std::map<std::string, pir_kernel_cfg> tuned;
+    std::atomic<bool> timing_on{false};
+    std::vector<TimedPair> pending;
+    std::vector<hipEvent_t> free_events;
+    pir_timing acc{};
+
+    ~Ctx();
+    int bind();
+    int acquire(Exec** out);
+    void release(Exec* e);
+    hipEvent_t take_event();
+    int plan_for(const Db& db, uint32_t q, const pir_kernel_cfg* cfg, Plan& p);
+    int enqueue_scan(const Db& db, const Plan& p, const uint32_t* d_sel, uint64_t stride_words, uint32_t q,
+                     uint8_t* d_out, uint8_t* partials, hipStream_t s);
+    std::string tune_key(const Geometry& g, uint32_t q) const;
+    void save_tune_cache();
+    void load_tune_cache();
+};
+
+int finish_plan(const Geometry& g, uint32_t q, Plan& p);
+size_t partial_bytes(const Geometry& g, const Plan& p, uint32_t q);
+
+}  // namespace pir

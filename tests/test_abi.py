@@ -1,0 +1,64 @@
+"""The C-ABI library loads and exports every function include/pir.h declares.
+No compute calls are made here (the CPU suite runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2509_06514_amd as pir
+from paper_2509_06514_amd import _native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "pir.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return set(re.findall(r"\b(pir_[a-z0-9_]+)\s*\(", text))
+
+
+def test_library_exports_every_declared_function():
+    lib = pir.lib()
+    declared = _header_functions()
+    assert len(declared) >= 25
+    for name in declared:
+        assert hasattr(lib, name), f"libpir.so does not export {name}"
+    assert declared == set(_native.SIGNATURES), "binding table and header disagree"
+
+
+def test_version_and_error_strings():
+    lib = pir.lib()
+    assert b"gfx950" in lib.pir_version()
+    assert lib.pir_last_error() is not None
+
+
+def test_null_arguments_rejected_without_device_work():
+    lib = pir.lib()
+    out = ctypes.c_void_p()
+    assert lib.pir_db_load(None, None, 1, 1, ctypes.byref(out)) == _native.PIR_E_INVAL
+    assert b"NULL" in lib.pir_last_error()
+    assert lib.pir_dpxor(None, None, None) == _native.PIR_E_INVAL
+    assert lib.pir_dpxor_batch(None, None, 0, 1, None) == _native.PIR_E_INVAL
+    assert lib.pir_dpxor_batch_async(None, None, 0, 1, None, None) == _native.PIR_E_INVAL
+    assert lib.pir_serve_create(None, None, ctypes.byref(out)) == _native.PIR_E_INVAL
+    assert lib.pir_serve_submit(None, 0, None, None, None) == _native.PIR_E_INVAL
+    assert lib.pir_db_min_sel_stride(None) == 0
+    assert lib.pir_host_alloc(0) is None
+
+
+def test_sel_stride_helper():
+    assert pir.sel_stride_for(1) == 256
+    assert pir.sel_stride_for(32 * 64) == 256
+    assert pir.sel_stride_for(32 * 64 + 1) == 512
+    assert pir.sel_stride_for(1 << 28, align=4) == (1 << 28) // 8
+
+
+@pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES") is None and os.path.exists("/dev/kfd"),
+                    reason="a GPU may be present; the no-device path is checked where there is none")
+def test_no_device_fails_loudly():
+    lib = pir.lib()
+    h = ctypes.c_void_p()
+    rc = lib.pir_ctx_create(0, ctypes.byref(h))
+    assert rc == _native.PIR_E_DEVICE
+    assert lib.pir_last_error()

@@ -1,0 +1,189 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit-exact.
+
+Every answer of dpXOR is unique (XOR over F_2 is exact), so the bar is
+equality of bytes everywhere.  Inputs come from the seeded generator only.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pir = pytest.importorskip("paper_2509_06514_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pir.Context(0)
+    yield c
+    c.close()
+
+
+def _dev_rows(sel_rows, n):
+    """Copy host selection rows into a device buffer with the library's row pitch."""
+    q = sel_rows.shape[0]
+    stride = pir.sel_stride_for(n)
+    host = np.zeros((q, stride), np.uint8)
+    w = min(sel_rows.shape[1], stride)
+    host[:, :w] = sel_rows[:, :w]
+    return torch.from_numpy(host).to("cuda:0"), stride
+
+
+def _flip(row, i):
+    r = row.copy()
+    r[i >> 3] ^= np.uint8(1 << (i & 7))
+    return r
+
+
+def test_c1_single_query_and_two_server_invariant(ctx):
+    # 2^20 records of 32 B (32 MiB), one Bernoulli(0.5) query; the e_i check
+    # for 16 random i: ans(b) XOR ans(b XOR e_i) = D[i].
+    n, r = 1 << 20, 32
+    dbh = synth.database(n, r, seed=synth.S_DB + 1)
+    db = ctx.load_db(dbh)
+    b = synth.selections(n, 1, seed=synth.S_SEL + 1)[0]
+    got = db.dpxor(b)
+    assert np.array_equal(got, oracle.dpxor(dbh, b))
+    idx = synth.indices(n, 16, seed=synth.S_IDX + 1)
+    rows = np.stack([b] + [_flip(b, i) for i in idx])
+    ans = db.dpxor_batch(rows)
+    assert np.array_equal(ans[0], got)
+    for k, i in enumerate(idx):
+        assert np.array_equal(ans[0] ^ ans[k + 1], dbh[i]), f"e_{i} reconstruction failed"
+    db.free()
+
+
+SHAPES = [(1, 1), (1, 32), (31, 3), (32, 32), (33, 1), (33, 33), (100, 2), (257, 4), (1000, 5),
+          (1000, 8), (4097, 16), (4097, 17), (5000, 31), (65537, 32), (3001, 48), (2049, 64),
+          (1234, 100), (777, 128), (10007, 256), (300, 1024), (65, 1000)]
+
+
+@pytest.mark.parametrize("n,r", SHAPES)
+def test_shape_grid_sync(ctx, n, r):
+    dbh = synth.database(n, r, seed=1000 + n + r)
+    db = ctx.load_db(dbh)
+    sel = synth.selections(n, 3, seed=2000 + n * 7 + r, tail_junk=True)
+    got = db.dpxor_batch(sel)
+    assert np.array_equal(got, oracle.dpxor_batch(dbh, sel))
+    assert np.array_equal(db.dpxor(sel[1]), oracle.dpxor(dbh, sel[1]))
+    db.free()
+
+
+@pytest.mark.parametrize("n,r", [(70001, 32), (9000, 7), (5003, 256), (3000, 96)])
+def test_special_selections(ctx, n, r):
+    dbh = synth.database(n, r, seed=77 + r)
+    db = ctx.load_db(dbh)
+    nb = (n + 7) // 8
+    zero = np.zeros(nb, np.uint8)
+    ones = np.full(nb, 0xFF, np.uint8)
+    assert not db.dpxor(zero).any()
+    assert np.array_equal(db.dpxor(ones), np.bitwise_xor.reduce(dbh, axis=0))
+    for i in (0, 31, 32, n - 1):
+        e = zero.copy()
+        e[i >> 3] = np.uint8(1 << (i & 7))
+        assert np.array_equal(db.dpxor(e), dbh[i])
+    db.free()
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 8, 16, 17, 33, 64])
+@pytest.mark.parametrize("n,r", [(50000, 32), (3333, 256), (20000, 8), (4000, 3)])
+def test_batch_async_default(ctx, n, r, q):
+    dbh = synth.database(n, r, seed=5 + n + r)
+    db = ctx.load_db(dbh)
+    sel = synth.selections(n, q, seed=900 + q)
+    want = oracle.dpxor_batch(dbh, sel)
+    d_sel, stride = _dev_rows(sel, n)
+    d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
+    db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride)
+    torch.cuda.synchronize()
+    assert np.array_equal(d_out.cpu().numpy(), want)
+    db.free()
+
+
+VALU_CFGS = [(1, 4), (1, 8), (1, 16), (2, 4), (2, 8), (4, 2), (4, 4), (4, 8), (8, 1), (8, 2), (8, 4),
+             (16, 1), (16, 2), (16, 4), (32, 1), (32, 2)]
+
+
+@pytest.mark.parametrize("n,r,q", [(40000, 32, 21), (2500, 128, 9), (9000, 4, 5)])
+def test_tile_invariance(ctx, n, r, q):
+    # every compiled (q_tile, unroll) and several grid sizes give identical bytes
+    dbh = synth.database(n, r, seed=31 * n + r)
+    db = ctx.load_db(dbh)
+    sel = synth.selections(n, q, seed=4242 + q)
+    want = oracle.dpxor_batch(dbh, sel)
+    d_sel, stride = _dev_rows(sel, n)
+    d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
+    for qt, u in VALU_CFGS:
+        for groups in (1, 7, 0):
+            d_out.fill_(0xEE)
+            db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride,
+                                 cfg=pir.KernelCfg(pir.PIR_VARIANT_VALU, qt, u, groups))
+            torch.cuda.synchronize()
+            assert np.array_equal(d_out.cpu().numpy(), want), (qt, u, groups)
+    db.free()
+
+
+def test_update_and_read_back(ctx):
+    n, r = 1000, 24
+    dbh = synth.database(n, r, seed=3)
+    db = ctx.load_db(dbh)
+    assert np.array_equal(db.read(0, n), dbh)
+    new = synth.database(77, r, seed=4)
+    db.update(45, new)
+    dbh2 = dbh.copy()
+    dbh2[45:122] = new
+    assert np.array_equal(db.read(0, n), dbh2)
+    assert np.array_equal(db.read(40, 10), dbh2[40:50])
+    sel = synth.selections(n, 4, seed=5)
+    assert np.array_equal(db.dpxor_batch(sel), oracle.dpxor_batch(dbh2, sel))
+    db.free()
+
+
+def test_repeat_runs_deterministic(ctx):
+    n, r, q = 200000, 32, 16
+    dbh = synth.database(n, r, seed=8)
+    db = ctx.load_db(dbh)
+    sel = synth.selections(n, q, seed=9)
+    d_sel, stride = _dev_rows(sel, n)
+    outs = []
+    for _ in range(3):
+        d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
+        db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride)
+        torch.cuda.synchronize()
+        outs.append(d_out.cpu().numpy())
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
+    assert np.array_equal(outs[0], oracle.dpxor_batch(dbh, sel))
+    db.free()
+
+
+def test_invalid_arguments(ctx):
+    n, r = 100, 32
+    dbh = synth.database(n, r, seed=1)
+    db = ctx.load_db(dbh)
+    d_sel = torch.zeros(256, dtype=torch.uint8, device="cuda:0")
+    d_out = torch.zeros(64, dtype=torch.uint8, device="cuda:0")
+    from paper_2509_06514_amd import _native
+    lib = pir.lib()
+    import ctypes
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    # stride not a multiple of 4, stride too small, q = 0, q too large
+    assert lib.pir_dpxor_batch_async(db.handle, ctypes.c_void_p(d_sel.data_ptr()), 6, 1,
+                                     ctypes.c_void_p(d_out.data_ptr()), s) == _native.PIR_E_INVAL
+    assert lib.pir_dpxor_batch_async(db.handle, ctypes.c_void_p(d_sel.data_ptr()), 0, 1,
+                                     ctypes.c_void_p(d_out.data_ptr()), s) == _native.PIR_E_INVAL
+    assert lib.pir_dpxor_batch_async(db.handle, ctypes.c_void_p(d_sel.data_ptr()), 256, 0,
+                                     ctypes.c_void_p(d_out.data_ptr()), s) == _native.PIR_E_INVAL
+    assert lib.pir_dpxor_batch_async(db.handle, ctypes.c_void_p(d_sel.data_ptr()), 256, 5000,
+                                     ctypes.c_void_p(d_out.data_ptr()), s) == _native.PIR_E_INVAL
+    h = ctypes.c_void_p()
+    assert lib.pir_db_load(ctx.handle, ctypes.c_void_p(dbh.ctypes.data), 0, 32,
+                           ctypes.byref(h)) == _native.PIR_E_INVAL
+    assert lib.pir_db_load(ctx.handle, ctypes.c_void_p(dbh.ctypes.data), 10, 0,
+                           ctypes.byref(h)) == _native.PIR_E_INVAL
+    assert lib.pir_db_update(db.handle, n - 1, 2, ctypes.c_void_p(dbh.ctypes.data)) == _native.PIR_E_INVAL
+    db.free()
