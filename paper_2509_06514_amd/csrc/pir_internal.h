@@ -44,11 +44,12 @@ struct Geometry {
 Geometry make_geometry(uint64_t n, uint32_t R);
 
 // One launch of the stage-1 scan.
+// Fields left 0 are filled in by finish_plan.
 struct Plan {
     uint32_t variant = PIR_VARIANT_VALU;
-    uint32_t qt = 1;        // queries per tile
-    uint32_t unroll = 4;    // units per wave iteration
-    uint32_t groups = 1;    // record groups (contiguous unit ranges)
+    uint32_t qt = 0;        // queries per tile
+    uint32_t unroll = 0;    // units per wave iteration
+    uint32_t groups = 0;    // record groups (contiguous unit ranges)
     uint32_t n_qt = 1;      // query tiles
     uint64_t units_per_group = 0;
     uint32_t grid = 0;      // workgroups launched

@@ -53,8 +53,17 @@ __device__ __forceinline__ uint32_t parity4(const u32x4& a) {
            ((__builtin_popcount(a.z) & 1u) << 2) | ((__builtin_popcount(a.w) & 1u) << 3);
 }
 
-// acc ^= d & s on four words (the compiler fuses each into one v_bitop3_b32).
-__device__ __forceinline__ void sel_xor(u32x4& acc, const u32x4& d, uint32_t s) { acc ^= d & s; }
+// acc ^= d & s on four words, one v_bitop3_b32 each.  The truth-table index
+// of v_bitop3 is (S0 << 2) | (S1 << 1) | S2, so S0 ^ (S1 & S2) is 0x78.
+__device__ __forceinline__ uint32_t xor_and(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x78);
+}
+__device__ __forceinline__ void sel_xor(u32x4& acc, const u32x4& d, uint32_t s) {
+    acc.x = xor_and(acc.x, d.x, s);
+    acc.y = xor_and(acc.y, d.y, s);
+    acc.z = xor_and(acc.z, d.z, s);
+    acc.w = xor_and(acc.w, d.w, s);
+}
 
 // Workgroup -> (record group, column tile, query tile).  Workgroups are
 // dispatched round-robin over the 8 XCDs; consecutive workgroups on one XCD
@@ -168,6 +177,213 @@ k_stage1_valu(const u32x4* __restrict__ db, const uint32_t* __restrict__ sel,
             }
         partials[((uint64_t)group * p.q_total + q0 + q) * p.rpad + byte_pos] = (uint8_t)x;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Stage 1, matrix-core variants (many queries).
+//
+// Over F_2, answer bit b of query q is the parity of
+//     C[q][b] = sum_j S[q][j] * Dbit[j][b],
+// an integer matrix product with 0/1 entries.  The matrix cores compute it
+// exactly: products are 0 or 1 and the sums are record counts (below 2^24
+// per workgroup, so exact in fp32; int32 in the int8 form), and the parity
+// of the count is the answer bit.  Nothing is approximated.
+//
+// Operands come straight from the bit-sliced layout: in one MFMA a lane holds
+// 32 k-elements (fp4) or 16 (int8) for one row or column.  Taking those k to
+// be the 32 records of one block makes a lane's A operand one selection word
+// of its query and its B operand one bit-sliced database word of its bit
+// column; each is spread to one element per bit.  Any fixed order of the 32
+// records inside a lane is fine as long as A and B use the same one.
+//
+// Work split: a workgroup owns (record group, column tile of 256 bit columns,
+// query tile of 16*MT queries); wave w owns bit columns [64w, 64w+64) of the
+// tile as 4 MFMA column tiles, and all MT row tiles.  A K-step covers 16
+// blocks: lane group g = lane/16 reads blocks kb+4g .. kb+4g+3, one per
+// sub-step s.  Column tile t of lane j is bit column 64w + 4j + t, so a lane
+// reads its 4 columns with one 16-byte load.
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x8 __attribute__((ext_vector_type(8)));
+
+constexpr uint32_t kMfmaBlocksPerStep = 16;
+
+// 32 bits -> 32 E2M1 values (1.0 = 0b0010 where the bit is set): dword t,
+// nibble n holds bit 4n + t.
+__device__ __forceinline__ i32x8 spread_fp4(uint32_t w) {
+    i32x8 r;
+    r[0] = (int32_t)((w << 1) & 0x22222222u);
+    r[1] = (int32_t)(w & 0x22222222u);
+    r[2] = (int32_t)((w >> 1) & 0x22222222u);
+    r[3] = (int32_t)((w >> 2) & 0x22222222u);
+    r[4] = 0;
+    r[5] = 0;
+    r[6] = 0;
+    r[7] = 0;
+    return r;
+}
+
+// 32 bits -> 32 int8 0/1 values in two 16-element halves: dword t, byte m
+// holds bit 8m + t (half 0: t = 0..3, half 1: t = 4..7).
+__device__ __forceinline__ void spread_i8(uint32_t w, i32x4& lo, i32x4& hi) {
+    lo[0] = (int32_t)(w & 0x01010101u);
+    lo[1] = (int32_t)((w >> 1) & 0x01010101u);
+    lo[2] = (int32_t)((w >> 2) & 0x01010101u);
+    lo[3] = (int32_t)((w >> 3) & 0x01010101u);
+    hi[0] = (int32_t)((w >> 4) & 0x01010101u);
+    hi[1] = (int32_t)((w >> 5) & 0x01010101u);
+    hi[2] = (int32_t)((w >> 6) & 0x01010101u);
+    hi[3] = (int32_t)((w >> 7) & 0x01010101u);
+}
+
+template <bool F4>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<true> {
+    typedef f32x4 type;
+};
+template <>
+struct MfmaAcc<false> {
+    typedef i32x4 type;
+};
+
+template <int MT, bool F4>
+__global__ void __launch_bounds__(kThreads)
+k_stage1_mfma(const uint32_t* __restrict__ db, const uint32_t* __restrict__ sel,
+              uint8_t* __restrict__ partials, Stage1Params p) {
+    typedef typename MfmaAcc<F4>::type acc_t;
+    uint32_t group, ct, qt;
+    if (!decode_block(p.groups, p.n_ct, p.n_qt, group, ct, qt)) return;
+
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t j = lane & 15, g = lane >> 4;
+    const uint32_t q0 = qt * (16 * MT);
+    const uint64_t block_words = 8ull * p.R;
+
+    // this lane's 4 bit columns (one 16-byte chunk) within every block
+    const u32x4* dl = reinterpret_cast<const u32x4*>(db + ct * 256 + wave * 64 + 4 * j);
+    const uint64_t block_chunks = block_words / 4;
+
+    // this lane's query row in each row tile (A operand row i = j)
+    const uint32_t* srow[MT];
+    bool qok[MT];
+#pragma unroll
+    for (int rt = 0; rt < MT; ++rt) {
+        const uint32_t q = q0 + 16 * rt + j;
+        qok[rt] = q < p.q_total;
+        srow[rt] = sel + (uint64_t)(qok[rt] ? q : 0) * p.stride_words;
+    }
+
+    acc_t acc[MT][4];
+#pragma unroll
+    for (int rt = 0; rt < MT; ++rt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[rt][t] = acc_t{0, 0, 0, 0};
+
+    const uint64_t b_begin = (uint64_t)group * p.units_per_group;
+    const uint64_t b_end = (b_begin + p.units_per_group < p.n_units) ? b_begin + p.units_per_group : p.n_units;
+
+    // One K-step's raw words: B chunk per sub-step, A word per (row tile, sub-step).
+    struct Step {
+        u32x4 bw[4];
+        uint32_t aw[MT][4];
+    };
+    auto load_full = [&](uint64_t kb, Step& st) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const uint64_t blk = kb + 4 * g + s;
+            st.bw[s] = dl[blk * block_chunks];
+#pragma unroll
+            for (int rt = 0; rt < MT; ++rt) st.aw[rt][s] = srow[rt][blk];
+        }
+    };
+    auto load_tail = [&](uint64_t kb, Step& st) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const uint64_t blk = kb + 4 * g + s;
+            const bool ok = blk < b_end;
+            st.bw[s] = ok ? dl[blk * block_chunks] : u32x4{0, 0, 0, 0};
+#pragma unroll
+            for (int rt = 0; rt < MT; ++rt) st.aw[rt][s] = ok ? srow[rt][blk] : 0u;
+        }
+    };
+    auto compute = [&](const Step& st) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (F4) {
+                i32x8 bx[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) bx[t] = spread_fp4(st.bw[s][t]);
+#pragma unroll
+                for (int rt = 0; rt < MT; ++rt) {
+                    const i32x8 ax = spread_fp4(qok[rt] ? st.aw[rt][s] : 0u);
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        acc[rt][t] = (acc_t)__builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                            ax, bx[t], (f32x4)acc[rt][t], 4, 4, 0, 127, 0, 127);
+                }
+            } else {
+                i32x4 blo[4], bhi[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) spread_i8(st.bw[s][t], blo[t], bhi[t]);
+#pragma unroll
+                for (int rt = 0; rt < MT; ++rt) {
+                    i32x4 alo, ahi;
+                    spread_i8(qok[rt] ? st.aw[rt][s] : 0u, alo, ahi);
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        acc[rt][t] = (acc_t)__builtin_amdgcn_mfma_i32_16x16x64_i8(alo, blo[t], (i32x4)acc[rt][t], 0, 0, 0);
+                        acc[rt][t] = (acc_t)__builtin_amdgcn_mfma_i32_16x16x64_i8(ahi, bhi[t], (i32x4)acc[rt][t], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    };
+
+    // Full K-steps, software-pipelined: the next step's loads are in flight
+    // while the current step runs on the matrix cores.  Then the ragged tail.
+    uint64_t kb = b_begin;
+    const uint64_t full_end = b_begin + (b_end - b_begin) / kMfmaBlocksPerStep * kMfmaBlocksPerStep;
+    if (kb < full_end) {
+        Step cur, nxt;
+        load_full(kb, cur);
+        for (; kb + kMfmaBlocksPerStep < full_end; kb += kMfmaBlocksPerStep) {
+            load_full(kb + kMfmaBlocksPerStep, nxt);
+            compute(cur);
+            cur = nxt;
+        }
+        compute(cur);
+        kb = full_end;
+    }
+    if (kb < b_end) {
+        Step st;
+        load_tail(kb, st);
+        compute(st);
+    }
+
+    // Output layout of a 16x16 MFMA tile: lane holds column j = lane % 16 and
+    // rows 4*(lane/16) + r, r = 0..3.  Row = query q0 + 16*rt + 4g + r; column
+    // tile t of lane j = bit column 64*wave + 4j + t = bit (4j + t) % 8 of
+    // byte 8*wave + j/2 of the tile.  Lanes j and j^1 fill one byte together.
+#pragma unroll
+    for (int rt = 0; rt < MT; ++rt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            uint32_t nib = 0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const uint32_t cnt = F4 ? (uint32_t)(float)acc[rt][t][r] : (uint32_t)acc[rt][t][r];
+                nib |= (cnt & 1u) << t;
+            }
+            const uint32_t other = (uint32_t)__shfl_xor((int)nib, 1);
+            const uint32_t q = q0 + 16 * rt + 4 * g + r;
+            if ((j & 1) == 0 && q < p.q_total) {
+                const uint32_t byte_pos = ct * 32 + wave * 8 + j / 2;
+                partials[((uint64_t)group * p.q_total + q) * p.rpad + byte_pos] = (uint8_t)(nib | (other << 4));
+            }
+        }
 }
 
 // Stage 2: out[q][m] = XOR over groups of partials[g][q][m].  Each workgroup
@@ -335,11 +551,48 @@ hipError_t launch_unslice(const Geometry& g, const uint32_t* src_block0, uint64_
     return hipGetLastError();
 }
 
-bool mfma_supported(uint32_t, const Geometry&, uint32_t, uint32_t) { return false; }
+bool mfma_supported(uint32_t variant, const Geometry& g, uint32_t qt, uint32_t unroll) {
+    if (variant != PIR_VARIANT_MFMA_F4 && variant != PIR_VARIANT_MFMA_I8) return false;
+    if (g.R % 32 != 0) return false;  // whole 256-column tiles
+    if (unroll != 4) return false;     // K-step of 16 blocks = 4 per lane group
+    return qt == 16 || qt == 32 || qt == 64;
+}
 
-hipError_t launch_stage1_mfma(const Geometry&, const Plan&, const void*, const uint32_t*, uint64_t,
-                              uint32_t, uint8_t*, hipStream_t) {
-    return hipErrorNotSupported;
+template <int MT, bool F4>
+static hipError_t launch_mfma_t(const Geometry& g, const Plan& pl, const void* db, const uint32_t* sel,
+                                uint64_t stride_words, uint32_t q, uint8_t* partials, hipStream_t s) {
+    Stage1Params p;
+    p.n_units = g.n_units;
+    p.units_per_group = pl.units_per_group;
+    p.stride_words = stride_words;
+    p.nb = g.nb;
+    p.q_total = q;
+    p.groups = pl.groups;
+    p.n_ct = g.n_ct;
+    p.n_qt = pl.n_qt;
+    p.cpb = g.cpb;
+    p.bpw = g.bpw;
+    p.lpb = g.lpb;
+    p.tile_bytes = g.tile_bytes;
+    p.R = g.R;
+    p.rpad = g.rpad;
+    const uint32_t total = pl.groups * g.n_ct * pl.n_qt;
+    const uint32_t grid = (total + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_stage1_mfma<MT, F4>), dim3(grid), dim3(kThreads), 0, s, (const uint32_t*)db, sel,
+                       partials, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage1_mfma(const Geometry& g, const Plan& p, const void* db, const uint32_t* sel,
+                              uint64_t stride_words, uint32_t q, uint8_t* partials, hipStream_t s) {
+    if (!mfma_supported(p.variant, g, p.qt, p.unroll)) return hipErrorInvalidValue;
+    const bool f4 = p.variant == PIR_VARIANT_MFMA_F4;
+    if (p.qt == 16) return f4 ? launch_mfma_t<1, true>(g, p, db, sel, stride_words, q, partials, s)
+                              : launch_mfma_t<1, false>(g, p, db, sel, stride_words, q, partials, s);
+    if (p.qt == 32) return f4 ? launch_mfma_t<2, true>(g, p, db, sel, stride_words, q, partials, s)
+                              : launch_mfma_t<2, false>(g, p, db, sel, stride_words, q, partials, s);
+    return f4 ? launch_mfma_t<4, true>(g, p, db, sel, stride_words, q, partials, s)
+              : launch_mfma_t<4, false>(g, p, db, sel, stride_words, q, partials, s);
 }
 
 Geometry make_geometry(uint64_t n, uint32_t R) {

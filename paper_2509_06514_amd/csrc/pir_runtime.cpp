@@ -105,8 +105,8 @@ int finish_plan(const Geometry& g, uint32_t q, Plan& p) {
         if (!valu_supported(p.qt, p.unroll))
             return fail(PIR_E_INVAL, "no VALU kernel for q_tile=%u unroll=%u", p.qt, p.unroll);
     } else if (p.variant == PIR_VARIANT_MFMA_I8 || p.variant == PIR_VARIANT_MFMA_F4) {
-        if (p.qt == 0) p.qt = 64;
-        if (p.unroll == 0) p.unroll = 1;
+        if (p.qt == 0) p.qt = q <= 16 ? 16 : (q <= 32 ? 32 : 64);
+        if (p.unroll == 0) p.unroll = 4;
         if (!mfma_supported(p.variant, g, p.qt, p.unroll))
             return fail(PIR_E_INVAL, "no MFMA kernel (variant %u) for R=%u q_tile=%u unroll=%u",
                         p.variant, g.R, p.qt, p.unroll);
@@ -123,6 +123,11 @@ int finish_plan(const Geometry& g, uint32_t q, Plan& p) {
         groups = std::max<uint64_t>(1, target_wg / co);
     }
     groups = std::min<uint64_t>(groups, std::max<uint64_t>(1, (g.n_units + min_units - 1) / min_units));
+    if (p.variant != PIR_VARIANT_VALU) {
+        // matrix-core counts are exact below 2^24 per accumulator: at most
+        // 2^19 blocks (2^24 records) per record group
+        groups = std::max<uint64_t>(groups, (g.n_units + (1ull << 19) - 1) >> 19);
+    }
     uint64_t upg = (g.n_units + groups - 1) / groups;
     upg = (upg + min_units - 1) / min_units * min_units;
     groups = (g.n_units + upg - 1) / upg;
@@ -631,20 +636,20 @@ int pir_tune(pir_db* d, uint32_t q, pir_kernel_cfg* out) {
     int rc = ctx->bind();
     if (rc) return rc;
     const Geometry& g = db->geo;
-    // candidates
+    // candidates: a query tile below min(q, 8) re-reads the database once per
+    // tile, so only tiles from min(q, 8) up are worth timing
     std::vector<pir_kernel_cfg> cands;
-    const uint32_t qts[] = {1, 2, 4, 8, 16, 32};
-    const uint32_t unrolls[] = {1, 2, 4, 8, 16};
-    for (uint32_t qt : qts) {
-        if (qt > pow2_ceil(q) || (qt > 1 && qt > q && qt / 2 >= q)) continue;
-        for (uint32_t u : unrolls)
+    const uint32_t qmax_tile = pow2_ceil(q);
+    const uint32_t qmin_tile = std::min<uint32_t>(qmax_tile, 8);
+    for (uint32_t qt : {1u, 2u, 4u, 8u, 16u, 32u}) {
+        if (qt > qmax_tile || qt < qmin_tile) continue;
+        for (uint32_t u : {1u, 2u, 4u, 8u, 16u})
             if (valu_supported(qt, u)) cands.push_back({PIR_VARIANT_VALU, qt, u, 0});
     }
     for (uint32_t v : {PIR_VARIANT_MFMA_I8, PIR_VARIANT_MFMA_F4})
         for (uint32_t qt : {16u, 32u, 64u})
-            for (uint32_t u : {1u, 2u})
-                if (q >= 8 && mfma_supported(v, g, qt, u)) cands.push_back({v, qt, u, 0});
-    // grid variants of each
+            if (q >= 8 && qt <= qmax_tile && mfma_supported(v, g, qt, 4)) cands.push_back({v, qt, 4, 0});
+    // grid variants of each: the default record-group count, half and double
     std::vector<pir_kernel_cfg> all;
     for (auto c : cands) {
         Plan p;
@@ -652,11 +657,9 @@ int pir_tune(pir_db* d, uint32_t q, pir_kernel_cfg* out) {
         p.qt = c.q_tile;
         p.unroll = c.unroll;
         if (finish_plan(g, q, p)) continue;
-        for (uint32_t mult : {1u, 2u}) {
+        for (uint32_t mult : {1u, 2u, 4u}) {
             pir_kernel_cfg cc = c;
             cc.groups = std::max<uint32_t>(1, p.groups * mult / 2);
-            all.push_back(cc);
-            cc.groups = p.groups * mult;
             all.push_back(cc);
         }
     }
@@ -676,6 +679,7 @@ int pir_tune(pir_db* d, uint32_t q, pir_kernel_cfg* out) {
     pir_kernel_cfg best_cfg{};
     DevBuf ws;
     const bool was_timing = ctx->timing_on.exchange(false);
+    const bool verbose = std::getenv("PIR_TUNE_VERBOSE") != nullptr;
     for (auto& c : all) {
         Plan p;
         p.variant = c.variant;
@@ -684,19 +688,27 @@ int pir_tune(pir_db* d, uint32_t q, pir_kernel_cfg* out) {
         p.groups = c.groups;
         if (finish_plan(g, q, p)) continue;
         if ((e = ws.ensure(partial_bytes(g, p, q))) != hipSuccess) continue;
+        // one untimed launch, one timed probe; candidates over 2x the best so far stop there
         rc = ctx->enqueue_scan(*db, p, (const uint32_t*)sel.ptr, stride / 4, q, (uint8_t*)outb.ptr,
                                (uint8_t*)ws.ptr, s);
         if (rc) continue;
-        const int reps = 3;
-        (void)hipEventRecord(a, s);
-        for (int i = 0; i < reps; ++i)
-            (void)ctx->enqueue_scan(*db, p, (const uint32_t*)sel.ptr, stride / 4, q, (uint8_t*)outb.ptr,
-                                    (uint8_t*)ws.ptr, s);
-        (void)hipEventRecord(b, s);
-        if (hipEventSynchronize(b) != hipSuccess) break;
         float ms = 0;
-        (void)hipEventElapsedTime(&ms, a, b);
-        ms /= reps;
+        int reps = 1;
+        for (int round = 0; round < 2; ++round) {
+            (void)hipEventRecord(a, s);
+            for (int i = 0; i < reps; ++i)
+                (void)ctx->enqueue_scan(*db, p, (const uint32_t*)sel.ptr, stride / 4, q, (uint8_t*)outb.ptr,
+                                        (uint8_t*)ws.ptr, s);
+            (void)hipEventRecord(b, s);
+            if (hipEventSynchronize(b) != hipSuccess) break;
+            (void)hipEventElapsedTime(&ms, a, b);
+            ms /= reps;
+            if (ms > 2.0f * best) break;
+            reps = 3;
+        }
+        if (verbose)
+            fprintf(stderr, "[pir_tune] q=%u variant=%u q_tile=%u unroll=%u groups=%u: %.4f ms\n", q, c.variant,
+                    c.q_tile, c.unroll, p.groups, ms);
         if (ms < best) {
             best = ms;
             best_cfg = c;

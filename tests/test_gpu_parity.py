@@ -187,3 +187,53 @@ def test_invalid_arguments(ctx):
                            ctypes.byref(h)) == _native.PIR_E_INVAL
     assert lib.pir_db_update(db.handle, n - 1, 2, ctypes.c_void_p(dbh.ctypes.data)) == _native.PIR_E_INVAL
     db.free()
+
+
+MFMA_VARIANTS = [pir.PIR_VARIANT_MFMA_F4, pir.PIR_VARIANT_MFMA_I8]
+
+
+@pytest.mark.parametrize("variant", MFMA_VARIANTS)
+@pytest.mark.parametrize("n,r", [(50000, 32), (4099, 64), (3333, 256), (1000, 1024), (70001, 128), (31, 32)])
+def test_mfma_variants(ctx, variant, n, r):
+    # the matrix-core forms (exact counts, then parity) give the oracle's bytes
+    dbh = synth.database(n, r, seed=7 * n + r + variant)
+    db = ctx.load_db(dbh)
+    qs = (1, 5, 16, 17, 33, 64, 100)
+    sel = synth.selections(n, max(qs), seed=600 + n + r)
+    want = oracle.dpxor_batch(dbh, sel)
+    d_sel, stride = _dev_rows(sel, n)
+    for q in qs:
+        d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
+        for qt in (16, 32, 64):
+            for groups in (0, 3):
+                d_out.fill_(0xEE)
+                db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride,
+                                     cfg=pir.KernelCfg(variant, qt, 4, groups))
+                torch.cuda.synchronize()
+                assert np.array_equal(d_out.cpu().numpy(), want[:q]), (q, qt, groups)
+    db.free()
+
+
+@pytest.mark.parametrize("variant", MFMA_VARIANTS)
+def test_mfma_counts_exact_on_large_group(ctx, variant):
+    # 2^25 records: one requested record group would hold 2^25 > 2^24 records;
+    # the planner splits it so fp32 counts stay exact.  All-ones selections
+    # make every count maximal.
+    n, r, q = 1 << 25, 32, 16
+    dbh = synth.database(n, r, seed=0xACE + variant)
+    db = ctx.load_db(dbh)
+    stride = pir.sel_stride_for(n)
+    host = np.full((q, stride), 0xFF, np.uint8)
+    want_all = np.bitwise_xor.reduce(dbh, axis=0)
+    rnd = synth.selections(n, 1, seed=0xBEE, stride=stride)
+    host[3] = rnd[0]
+    d_sel = torch.from_numpy(host).to("cuda:0")
+    d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
+    db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride, cfg=pir.KernelCfg(variant, 16, 4, 1))
+    torch.cuda.synchronize()
+    got = d_out.cpu().numpy()
+    for i in range(q):
+        if i != 3:
+            assert np.array_equal(got[i], want_all), i
+    assert np.array_equal(got[3], oracle.dpxor(dbh, rnd[0]))
+    db.free()
