@@ -209,6 +209,20 @@ typedef int32_t i32x8 __attribute__((ext_vector_type(8)));
 
 constexpr uint32_t kMfmaBlocksPerStep = 16;
 
+// s_waitcnt with vmcnt <= N and no wait on the other counters (gfx9
+// encoding: vmcnt[3:0] bits 3:0, vmcnt[5:4] bits 15:14, expcnt 6:4,
+// lgkmcnt 11:8).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+// Workgroup barrier without the memory fences of __syncthreads (which would
+// wait for every load in flight); the clobber keeps LDS accesses on their
+// side of it.
+__device__ __forceinline__ void wg_barrier() { asm volatile("s_barrier" ::: "memory"); }
+
 // 32 bits -> 32 E2M1 values (1.0 = 0b0010 where the bit is set): dword t,
 // nibble n holds bit 4n + t.
 __device__ __forceinline__ i32x8 spread_fp4(uint32_t w) {
@@ -351,6 +365,10 @@ k_stage1_mfma(const uint32_t* __restrict__ db, const uint32_t* __restrict__ sel,
         load_full(kb, cur);
         for (; kb + kMfmaBlocksPerStep < full_end; kb += kMfmaBlocksPerStep) {
             load_full(kb + kMfmaBlocksPerStep, nxt);
+            // keep the loads issued here, ahead of the matrix work (the
+            // scheduler would otherwise sink them past it)
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_sched_barrier(0);
             compute(cur);
             cur = nxt;
         }
@@ -385,6 +403,239 @@ k_stage1_mfma(const uint32_t* __restrict__ db, const uint32_t* __restrict__ sel,
             }
         }
 }
+
+// Operand reads of one K-step from an LDS stage: four database chunks at
+// `b` + 0/1/2/3 KiB and MT selection quads at `a` + rt KiB.  The reads and
+// their lgkmcnt wait sit in one asm block, so the values are complete when
+// the block ends; the stage is known to be filled by the caller's vmcnt wait
+// and barrier.
+template <int MT>
+__device__ __forceinline__ void lds_read_step(uint32_t b, uint32_t a, u32x4 (&bw)[4], u32x4 (&aw)[MT]) {
+    if constexpr (MT == 1) {
+        asm volatile(
+            "ds_read_b128 %0, %5\n\t"
+            "ds_read_b128 %1, %5 offset:1024\n\t"
+            "ds_read_b128 %2, %5 offset:2048\n\t"
+            "ds_read_b128 %3, %5 offset:3072\n\t"
+            "ds_read_b128 %4, %6\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(bw[0]), "=&v"(bw[1]), "=&v"(bw[2]), "=&v"(bw[3]), "=&v"(aw[0])
+            : "v"(b), "v"(a));
+    } else if constexpr (MT == 2) {
+        asm volatile(
+            "ds_read_b128 %0, %6\n\t"
+            "ds_read_b128 %1, %6 offset:1024\n\t"
+            "ds_read_b128 %2, %6 offset:2048\n\t"
+            "ds_read_b128 %3, %6 offset:3072\n\t"
+            "ds_read_b128 %4, %7\n\t"
+            "ds_read_b128 %5, %7 offset:1024\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(bw[0]), "=&v"(bw[1]), "=&v"(bw[2]), "=&v"(bw[3]), "=&v"(aw[0]), "=&v"(aw[1])
+            : "v"(b), "v"(a));
+    } else {
+        static_assert(MT == 4, "row tiles");
+        asm volatile(
+            "ds_read_b128 %0, %8\n\t"
+            "ds_read_b128 %1, %8 offset:1024\n\t"
+            "ds_read_b128 %2, %8 offset:2048\n\t"
+            "ds_read_b128 %3, %8 offset:3072\n\t"
+            "ds_read_b128 %4, %9\n\t"
+            "ds_read_b128 %5, %9 offset:1024\n\t"
+            "ds_read_b128 %6, %9 offset:2048\n\t"
+            "ds_read_b128 %7, %9 offset:3072\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(bw[0]), "=&v"(bw[1]), "=&v"(bw[2]), "=&v"(bw[3]), "=&v"(aw[0]), "=&v"(aw[1]),
+              "=&v"(aw[2]), "=&v"(aw[3])
+            : "v"(b), "v"(a));
+    }
+}
+
+// Matrix-core scan with a multi-stage LDS ring.  Direct-to-LDS loads
+// (global_load_lds_dwordx4 / _dword) stream the next S-1 K-steps of database
+// chunks and selection words into LDS while the current K-step runs on the
+// matrix cores, so the bytes in flight do not cost registers.  Per K-step a
+// stage holds the workgroup's 16 blocks x 256 bit columns (16 KiB) and its
+// 16*MT query rows x 16 selection words.  Each wave waits for its own loads
+// of the step (vmcnt) and a barrier makes every wave's part visible; the
+// same barrier tells the wave that refills a stage that it has been read.
+template <int MT, bool F4, int S>
+__global__ void __launch_bounds__(kThreads)
+k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ sel,
+                  uint8_t* __restrict__ partials, Stage1Params p) {
+    typedef typename MfmaAcc<F4>::type acc_t;
+    constexpr int QT = 16 * MT;
+    constexpr int kLoadsPerStep = 4 + MT;  // per wave: 4 database chunks + MT selection rows-of-4
+    static_assert(S == 3, "three ring stages");
+    // one LDS object per stage: accesses to different stages are then known
+    // not to alias, so reads of one stage do not wait for loads into another
+    __shared__ __attribute__((aligned(16))) uint32_t lds_db0[16][256];
+    __shared__ __attribute__((aligned(16))) uint32_t lds_db1[16][256];
+    __shared__ __attribute__((aligned(16))) uint32_t lds_db2[16][256];
+    __shared__ __attribute__((aligned(16))) uint32_t lds_sel0[QT][16];
+    __shared__ __attribute__((aligned(16))) uint32_t lds_sel1[QT][16];
+    __shared__ __attribute__((aligned(16))) uint32_t lds_sel2[QT][16];
+    // (a macro, not a lambda: a lambda returning these arrays keeps clang
+    // from emitting the kernel's host launch stub)
+#define PIR_STAGE_DB(slot) ((slot) == 0 ? lds_db0 : ((slot) == 1 ? lds_db1 : lds_db2))
+#define PIR_STAGE_SEL(slot) ((slot) == 0 ? lds_sel0 : ((slot) == 1 ? lds_sel1 : lds_sel2))
+
+    uint32_t group, ct, qt;
+    if (!decode_block(p.groups, p.n_ct, p.n_qt, group, ct, qt)) return;
+
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t j = lane & 15, g = lane >> 4;
+    const uint32_t q0 = qt * QT;
+    const uint64_t block_words = 8ull * p.R;
+
+    bool qok[MT];
+#pragma unroll
+    for (int rt = 0; rt < MT; ++rt) qok[rt] = q0 + 16 * rt + j < p.q_total;
+
+    // loader geometry: database chunk of lane l = words 4l..4l+3 of the tile;
+    // selection row (4i + l/16), word l%16 of the step
+    const uint32_t* db_src = db + ct * 256 + 4 * lane;
+    const uint32_t* sel_src[MT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+        const uint32_t row = 4 * (wave + 4 * i) + lane / 16;  // 0 .. QT-1
+        const uint32_t q = q0 + row < p.q_total ? q0 + row : q0;
+        sel_src[i] = sel + (uint64_t)q * p.stride_words + (lane & 15);
+    }
+    auto issue = [&](uint64_t kb, int slot) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t b = 4 * i + wave;
+            __builtin_amdgcn_global_load_lds(db_src + (kb + b) * block_words, &PIR_STAGE_DB(slot)[b][0], 16, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+            __builtin_amdgcn_global_load_lds(sel_src[i] + kb, &PIR_STAGE_SEL(slot)[4 * (wave + 4 * i)][0], 4, 0, 0);
+    };
+
+    acc_t acc[MT][4];
+#pragma unroll
+    for (int rt = 0; rt < MT; ++rt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[rt][t] = acc_t{0, 0, 0, 0};
+
+    auto mma = [&](const u32x4 bw[4], const u32x4 aw4[MT]) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (F4) {
+                i32x8 bx[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) bx[t] = spread_fp4(bw[s][t]);
+#pragma unroll
+                for (int rt = 0; rt < MT; ++rt) {
+                    const i32x8 ax = spread_fp4(qok[rt] ? aw4[rt][s] : 0u);
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        acc[rt][t] = (acc_t)__builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                            ax, bx[t], (f32x4)acc[rt][t], 4, 4, 0, 127, 0, 127);
+                }
+            } else {
+                i32x4 blo[4], bhi[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) spread_i8(bw[s][t], blo[t], bhi[t]);
+#pragma unroll
+                for (int rt = 0; rt < MT; ++rt) {
+                    i32x4 alo, ahi;
+                    spread_i8(qok[rt] ? aw4[rt][s] : 0u, alo, ahi);
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        acc[rt][t] = (acc_t)__builtin_amdgcn_mfma_i32_16x16x64_i8(alo, blo[t], (i32x4)acc[rt][t], 0, 0, 0);
+                        acc[rt][t] = (acc_t)__builtin_amdgcn_mfma_i32_16x16x64_i8(ahi, bhi[t], (i32x4)acc[rt][t], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    };
+    auto compute_slot = [&](int slot) {
+        u32x4 bw[4], aw4[MT];
+        const uint32_t b = (uint32_t)(uintptr_t)&PIR_STAGE_DB(slot)[4 * g][64 * wave + 4 * j];
+        const uint32_t a = (uint32_t)(uintptr_t)&PIR_STAGE_SEL(slot)[j][4 * g];
+        lds_read_step<MT>(b, a, bw, aw4);
+        mma(bw, aw4);
+    };
+
+    const uint64_t b_begin = (uint64_t)group * p.units_per_group;
+    const uint64_t b_end = (b_begin + p.units_per_group < p.n_units) ? b_begin + p.units_per_group : p.n_units;
+    const uint64_t nsteps = (b_end - b_begin) / kMfmaBlocksPerStep;
+
+    // prologue: steps 0 .. S-2 in flight
+#pragma unroll
+    for (int k = 0; k < S - 1; ++k)
+        if ((uint64_t)k < nsteps) issue(b_begin + k * kMfmaBlocksPerStep, k);
+
+    uint64_t k = 0;
+    // Steady state: every step issues the load of step k+S-1, so the body is
+    // straight-line code (one basic block) and the per-step scheduling
+    // barriers hold.  Unrolled by S so every stage index is a constant.
+    for (; k + 2 * S - 2 < nsteps; k += S) {
+#pragma unroll
+        for (int u = 0; u < S; ++u) {
+            wait_vmcnt<(S - 2) * kLoadsPerStep>();  // own loads of step k+u have landed
+            wg_barrier();                            // ... and everyone's; stage u-1 is free
+            issue(b_begin + (k + u + S - 1) * kMfmaBlocksPerStep, (u + S - 1) % S);
+            compute_slot(u);
+            __builtin_amdgcn_sched_barrier(0);       // keep this step's matrix work here
+        }
+    }
+    // last steps (fewer than 2S-1): same ring, with bounds
+    for (; k < nsteps; k += S) {
+#pragma unroll
+        for (int u = 0; u < S; ++u) {
+            if (k + u < nsteps) {
+                wait_vmcnt<0>();
+                wg_barrier();
+                if (k + u + S - 1 < nsteps) issue(b_begin + (k + u + S - 1) * kMfmaBlocksPerStep, (u + S - 1) % S);
+                compute_slot(u);
+            }
+        }
+    }
+    k = nsteps;
+
+    // ragged tail (fewer than 16 blocks) straight from memory
+    const uint64_t kb = b_begin + k * kMfmaBlocksPerStep;
+    if (kb < b_end) {
+        const u32x4* dl = reinterpret_cast<const u32x4*>(db + ct * 256 + wave * 64 + 4 * j);
+        u32x4 bw[4], aw4[MT];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const uint64_t blk = kb + 4 * g + s;
+            const bool ok = blk < b_end;
+            bw[s] = ok ? dl[blk * (block_words / 4)] : u32x4{0, 0, 0, 0};
+#pragma unroll
+            for (int rt = 0; rt < MT; ++rt) {
+                const uint32_t q = q0 + 16 * rt + j;
+                aw4[rt][s] = (ok && q < p.q_total) ? sel[(uint64_t)q * p.stride_words + blk] : 0u;
+            }
+        }
+        mma(bw, aw4);
+    }
+
+#pragma unroll
+    for (int rt = 0; rt < MT; ++rt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            uint32_t nib = 0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const uint32_t cnt = F4 ? (uint32_t)(float)acc[rt][t][r] : (uint32_t)acc[rt][t][r];
+                nib |= (cnt & 1u) << t;
+            }
+            const uint32_t other = (uint32_t)__shfl_xor((int)nib, 1);
+            const uint32_t q = q0 + 16 * rt + 4 * g + r;
+            if ((j & 1) == 0 && q < p.q_total) {
+                const uint32_t byte_pos = ct * 32 + wave * 8 + j / 2;
+                partials[((uint64_t)group * p.q_total + q) * p.rpad + byte_pos] = (uint8_t)(nib | (other << 4));
+            }
+        }
+}
+
+#undef PIR_STAGE_DB
+#undef PIR_STAGE_SEL
 
 // Stage 2: out[q][m] = XOR over groups of partials[g][q][m].  Each workgroup
 // owns `wpb` consecutive 32-bit words of the [q][rpad] result and splits the
@@ -554,7 +805,9 @@ hipError_t launch_unslice(const Geometry& g, const uint32_t* src_block0, uint64_
 bool mfma_supported(uint32_t variant, const Geometry& g, uint32_t qt, uint32_t unroll) {
     if (variant != PIR_VARIANT_MFMA_F4 && variant != PIR_VARIANT_MFMA_I8) return false;
     if (g.R % 32 != 0) return false;  // whole 256-column tiles
-    if (unroll != 4) return false;     // K-step of 16 blocks = 4 per lane group
+    // unroll selects the pipeline: 4 = one K-step ahead in registers,
+    // 8 = two K-steps ahead through a 3-stage LDS ring
+    if (unroll != 4 && unroll != 8) return false;
     return qt == 16 || qt == 32 || qt == 64;
 }
 
@@ -578,8 +831,12 @@ static hipError_t launch_mfma_t(const Geometry& g, const Plan& pl, const void* d
     p.rpad = g.rpad;
     const uint32_t total = pl.groups * g.n_ct * pl.n_qt;
     const uint32_t grid = (total + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_stage1_mfma<MT, F4>), dim3(grid), dim3(kThreads), 0, s, (const uint32_t*)db, sel,
-                       partials, p);
+    if (pl.unroll == 8)
+        hipLaunchKernelGGL((k_stage1_mfma_lds<MT, F4, 3>), dim3(grid), dim3(kThreads), 0, s, (const uint32_t*)db,
+                           sel, partials, p);
+    else
+        hipLaunchKernelGGL((k_stage1_mfma<MT, F4>), dim3(grid), dim3(kThreads), 0, s, (const uint32_t*)db, sel,
+                           partials, p);
     return hipGetLastError();
 }
 

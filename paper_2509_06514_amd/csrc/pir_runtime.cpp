@@ -115,8 +115,9 @@ int finish_plan(const Geometry& g, uint32_t q, Plan& p) {
     }
     p.n_qt = (q + p.qt - 1) / p.qt;
     const uint64_t co = (uint64_t)g.n_ct * p.n_qt;
-    // smallest slice of units worth a workgroup: one full iteration of its 4 waves
-    const uint64_t min_units = 4ull * p.unroll;
+    // smallest slice of units worth a workgroup: one full iteration of its 4
+    // waves (VALU), one K-step of 16 blocks (matrix cores)
+    const uint64_t min_units = p.variant == PIR_VARIANT_VALU ? 4ull * p.unroll : 16ull;
     uint64_t groups = p.groups;
     if (groups == 0) {
         const uint64_t target_wg = 2048;  // 256 CUs x 8 resident workgroups
@@ -648,7 +649,8 @@ int pir_tune(pir_db* d, uint32_t q, pir_kernel_cfg* out) {
     }
     for (uint32_t v : {PIR_VARIANT_MFMA_I8, PIR_VARIANT_MFMA_F4})
         for (uint32_t qt : {16u, 32u, 64u})
-            if (q >= 8 && qt <= qmax_tile && mfma_supported(v, g, qt, 4)) cands.push_back({v, qt, 4, 0});
+            for (uint32_t u : {4u, 8u})
+                if (q >= 8 && qt <= qmax_tile && mfma_supported(v, g, qt, u)) cands.push_back({v, qt, u, 0});
     // grid variants of each: the default record-group count, half and double
     std::vector<pir_kernel_cfg> all;
     for (auto c : cands) {

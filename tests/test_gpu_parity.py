@@ -205,12 +205,13 @@ def test_mfma_variants(ctx, variant, n, r):
     for q in qs:
         d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
         for qt in (16, 32, 64):
-            for groups in (0, 3):
-                d_out.fill_(0xEE)
-                db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride,
-                                     cfg=pir.KernelCfg(variant, qt, 4, groups))
-                torch.cuda.synchronize()
-                assert np.array_equal(d_out.cpu().numpy(), want[:q]), (q, qt, groups)
+            for unroll in (4, 8):  # register pipeline, LDS ring
+                for groups in (0, 3, 1):
+                    d_out.fill_(0xEE)
+                    db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride,
+                                         cfg=pir.KernelCfg(variant, qt, unroll, groups))
+                    torch.cuda.synchronize()
+                    assert np.array_equal(d_out.cpu().numpy(), want[:q]), (q, qt, unroll, groups)
     db.free()
 
 
@@ -229,11 +230,14 @@ def test_mfma_counts_exact_on_large_group(ctx, variant):
     host[3] = rnd[0]
     d_sel = torch.from_numpy(host).to("cuda:0")
     d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
-    db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride, cfg=pir.KernelCfg(variant, 16, 4, 1))
-    torch.cuda.synchronize()
-    got = d_out.cpu().numpy()
-    for i in range(q):
-        if i != 3:
-            assert np.array_equal(got[i], want_all), i
-    assert np.array_equal(got[3], oracle.dpxor(dbh, rnd[0]))
+    want3 = oracle.dpxor(dbh, rnd[0])
+    for unroll in (4, 8):
+        d_out.fill_(0)
+        db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride, cfg=pir.KernelCfg(variant, 16, unroll, 1))
+        torch.cuda.synchronize()
+        got = d_out.cpu().numpy()
+        for i in range(q):
+            if i != 3:
+                assert np.array_equal(got[i], want_all), (unroll, i)
+        assert np.array_equal(got[3], want3), unroll
     db.free()
