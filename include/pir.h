@@ -219,6 +219,8 @@ typedef struct pir_serve_stats {
     double qps;               /* completed / elapsed_s */
     uint64_t batch_hist[13];  /* batches with size in [2^i, 2^(i+1)) */
     uint64_t h2d_bytes;       /* selection bytes uploaded */
+    uint32_t max_inflight;    /* most slots busy at once (batches overlapping on the device) */
+    uint32_t n_slots;
 } pir_serve_stats;
 
 int pir_serve_create(pir_ctx* ctx, const pir_serve_config* cfg, pir_server** out);

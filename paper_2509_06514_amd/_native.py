@@ -59,7 +59,8 @@ class pir_serve_stats(ctypes.Structure):
                 ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
                 ("mean_us", ctypes.c_double), ("max_us", ctypes.c_double),
                 ("elapsed_s", ctypes.c_double), ("qps", ctypes.c_double),
-                ("batch_hist", ctypes.c_uint64 * 13), ("h2d_bytes", ctypes.c_uint64)]
+                ("batch_hist", ctypes.c_uint64 * 13), ("h2d_bytes", ctypes.c_uint64),
+                ("max_inflight", ctypes.c_uint32), ("n_slots", ctypes.c_uint32)]
 
 
 _P = ctypes.c_void_p

@@ -88,6 +88,7 @@ struct Server {
     std::vector<double> lat_us;
     uint64_t submitted = 0, completed = 0, rejected = 0, batches = 0, h2d_bytes = 0;
     uint64_t hist[13] = {0};
+    uint32_t max_inflight = 0;
     Clock::time_point t0;
 
     void run();
@@ -191,6 +192,9 @@ bool Server::dispatch_one(Slot& s) {
         return true;
     }
     s.busy = true;
+    uint32_t inflight = 0;
+    for (auto& sp : slots) inflight += sp->busy ? 1 : 0;
+    max_inflight = std::max(max_inflight, inflight);
     return true;
 }
 
@@ -386,6 +390,8 @@ int pir_serve_stats_get(pir_server* sv, pir_serve_stats* out, int reset) {
     out->batches = srv->batches;
     out->h2d_bytes = srv->h2d_bytes;
     for (int i = 0; i < 13; ++i) out->batch_hist[i] = srv->hist[i];
+    out->max_inflight = srv->max_inflight;
+    out->n_slots = (uint32_t)srv->slots.size();
     out->elapsed_s = std::chrono::duration<double>(Clock::now() - srv->t0).count();
     out->qps = out->elapsed_s > 0 ? (double)srv->completed / out->elapsed_s : 0.0;
     if (!srv->lat_us.empty()) {
@@ -409,6 +415,7 @@ int pir_serve_stats_get(pir_server* sv, pir_serve_stats* out, int reset) {
         srv->lat_us.clear();
         srv->submitted = srv->completed = srv->rejected = srv->batches = srv->h2d_bytes = 0;
         for (auto& h : srv->hist) h = 0;
+        srv->max_inflight = 0;
         srv->t0 = Clock::now();
     }
     return PIR_OK;

@@ -1,0 +1,130 @@
+"""Parity at the full workload sizes, in the launch configurations the
+benchmark times (tuned plans, same seeds as bench.py).
+
+The oracle computes sampled rows one by one (each is a full database scan on
+one host thread); every other row is checked by properties that hold at any
+size: rows from different kernel variants must be identical, and the
+two-server identity ans(b) XOR ans(b XOR e_i) = D[i].
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pir = pytest.importorskip("paper_2509_06514_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pir.Context(0)
+    yield c
+    c.close()
+
+
+def _run(db, d_sel, stride, q, cfg=None):
+    out = torch.empty((q, db.record_bytes), dtype=torch.uint8, device="cuda:0")
+    out.fill_(0xEE)
+    db.dpxor_batch_async(d_sel, q, out, sel_stride=stride, cfg=cfg)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def c4(ctx):
+    # 2^28 records x 32 B = 8 GiB, the benchmark's database and selections
+    n, r = 1 << 28, 32
+    dbh = synth.database(n, r, seed=synth.S_DB + 3)
+    db = ctx.load_db(dbh)
+    stride = pir.sel_stride_for(n)
+    sel = synth.selections(n, 512, seed=synth.S_SEL + 3, stride=stride)
+    d_sel = torch.from_numpy(sel).to("cuda:0")
+    rows = {i: oracle.dpxor(dbh, sel[i]) for i in (0, 63, 511)}
+    yield dbh, db, sel, d_sel, stride, rows
+    del d_sel
+    db.free()
+
+
+@pytest.mark.parametrize("q", [1, 16, 64, 512])
+def test_c4_tuned_plan_matches_oracle_rows(c4, q):
+    dbh, db, sel, d_sel, stride, rows = c4
+    cfg = db.tune(q)  # what bench.py does before timing
+    assert db.get_cfg(q).as_dict() == cfg.as_dict()
+    got = _run(db, d_sel, stride, q)  # default path = the tuned plan
+    for i, want in rows.items():
+        if i < q:
+            assert np.array_equal(got[i], want), (q, i, cfg)
+    assert got.any()
+
+
+@pytest.mark.parametrize("q", [64, 512])
+def test_c4_variants_agree(c4, q):
+    # bitwise select-XOR, int8 matrix cores and fp4 matrix cores: identical rows
+    dbh, db, sel, d_sel, stride, rows = c4
+    ref = _run(db, d_sel, stride, q, pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 8, 0))
+    for i, want in rows.items():
+        if i < q:
+            assert np.array_equal(ref[i], want)
+    for cfg in (pir.KernelCfg(pir.PIR_VARIANT_MFMA_I8, 64, 8, 0),
+                pir.KernelCfg(pir.PIR_VARIANT_MFMA_I8, 32, 4, 0),
+                pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 32, 4, 0),
+                pir.KernelCfg(pir.PIR_VARIANT_VALU, 16, 4, 0)):
+        got = _run(db, d_sel, stride, q, cfg)
+        assert np.array_equal(got, ref), cfg
+
+
+def test_c4_two_server_identity(c4):
+    # for random b and b XOR e_i (16 random i): ans(b) XOR ans(b XOR e_i) = D[i]
+    dbh, db, sel, d_sel, stride, rows = c4
+    n = dbh.shape[0]
+    idx = synth.indices(n, 16, seed=synth.S_IDX + 3)
+    pair = np.empty((1 + len(idx), stride), np.uint8)
+    pair[0] = sel[0]
+    for k, i in enumerate(idx):
+        pair[k + 1] = sel[0]
+        pair[k + 1, i >> 3] ^= np.uint8(1 << (i & 7))
+    d_pair = torch.from_numpy(pair).to("cuda:0")
+    ans = _run(db, d_pair, stride, pair.shape[0])
+    assert np.array_equal(ans[0], rows[0])
+    for k, i in enumerate(idx):
+        assert np.array_equal(ans[0] ^ ans[k + 1], dbh[i]), i
+
+
+def test_c2_single_query_full_compare(ctx):
+    # 2^25 records x 32 B (1 GiB): the single-query roofline configuration
+    n, r = 1 << 25, 32
+    dbh = synth.database(n, r, seed=synth.S_DB + 2)
+    db = ctx.load_db(dbh)
+    stride = pir.sel_stride_for(n)
+    sel = synth.selections(n, 1, seed=synth.S_SEL + 2, stride=stride)
+    db.tune(1)
+    got = _run(db, torch.from_numpy(sel).to("cuda:0"), stride, 1)
+    assert np.array_equal(got[0], oracle.dpxor(dbh, sel[0]))
+    assert np.array_equal(db.dpxor(sel[0][: (n + 7) // 8]), got[0])
+    db.free()
+
+
+def test_c3_batched_rows(ctx):
+    # 2^23 records x 256 B (2 GiB), Q in {8, 64, 256} in one pass each
+    n, r = 1 << 23, 256
+    dbh = synth.database(n, r, seed=synth.S_DB + 4)
+    db = ctx.load_db(dbh)
+    stride = pir.sel_stride_for(n)
+    sel = synth.selections(n, 256, seed=synth.S_SEL + 4, stride=stride)
+    d_sel = torch.from_numpy(sel).to("cuda:0")
+    rows = {i: oracle.dpxor(dbh, sel[i]) for i in (0, 7, 255)}
+    for q in (8, 64, 256):
+        db.tune(q)
+        got = _run(db, d_sel, stride, q)
+        for i, want in rows.items():
+            if i < q:
+                assert np.array_equal(got[i], want), (q, i)
+        if q == 256:
+            alt = _run(db, d_sel, stride, q, pir.KernelCfg(pir.PIR_VARIANT_VALU, 16, 4, 0))
+            assert np.array_equal(alt, got)
+    db.free()
