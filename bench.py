@@ -48,8 +48,20 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(name, q):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they match this kernel."""
+def kernel_name(cfg, r):
+    """Name of the stage-1 kernel instance a plan launches (as profilers print it)."""
+    if cfg.variant == 1:
+        return f"k_stage1_valu<{cfg.q_tile}, {cfg.unroll}, {'true' if r < 32 else 'false'}>"
+    mt = cfg.q_tile // 16
+    f4 = "true" if cfg.variant == 3 else "false"
+    if cfg.unroll == 8:
+        return f"k_stage1_mfma_lds<{mt}, {f4}, 3>"
+    return f"k_stage1_mfma<{mt}, {f4}>"
+
+
+def load_traffic(name, q, cfg, r):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they are for this kernel
+    (same source hash, same kernel instance); else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
     try:
         with open(path) as f:
@@ -58,6 +70,8 @@ def load_traffic(name, q):
         return None
     entry = t.get(f"q{q}")
     if not entry or t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    if entry.get("kernel") != kernel_name(cfg, r):
         return None
     return entry.get("hbm_bytes_per_launch")
 
@@ -126,6 +140,96 @@ def cpu_baseline(db_host, sel_rows, n, r, sample_queries):
             "db_gbs_scanned": sample_queries * n * r / dt / 1e9}
 
 
+SERVE_DBS = [(1 << 23, 32), (1 << 24, 128), (1 << 22, 1024)]
+
+
+def serve_bench(args):
+    """Open-loop Poisson arrivals over three resident databases (continuous batching).
+
+    Each rate runs for args.serve_seconds; each request goes to a database
+    drawn uniformly; selections come from a pre-generated pool per database
+    (contents do not change the scan's cost).  Latency is submit -> answer in
+    host memory, measured by the server.
+    """
+    import threading
+
+    import numpy as np
+
+    import synth
+    import paper_2509_06514_amd as pir
+
+    ctx = pir.Context(0)
+    hosts, dbs = [], []
+    for k, (n, r) in enumerate(SERVE_DBS):
+        h = synth.database(n, r, seed=synth.S_DB + 5 + k)
+        dbs.append(ctx.load_db(h))
+        hosts.append(h)
+        log(f"serve: loaded DB{k} N={n} R={r}")
+    pool = [synth.selections(n, 16, seed=synth.S_SEL + 50 + k) for k, (n, r) in enumerate(SERVE_DBS)]
+    results = []
+    rates = [int(x) for x in args.serve_rates.split(",")]
+    threads_n = args.serve_threads
+    for rate in rates:
+        srv = pir.Server(ctx, q_max=args.serve_qmax, max_wait_us=args.serve_wait_us, n_slots=args.serve_slots,
+                         queue_cap=1 << 20)
+        ids = [srv.add_db(d) for d in dbs]
+        # warm the plans for every batch size the server can form
+        for d in dbs:
+            d.tune(args.serve_qmax)
+        outs = [np.zeros((4096, r), np.uint8) for (n, r) in SERVE_DBS]
+        stop_at = time.perf_counter() + args.serve_seconds
+        pending = [[] for _ in range(threads_n)]
+        rejected = [0] * threads_n
+
+        def submitter(tid):
+            rng = np.random.default_rng(1000 * rate + tid)
+            t = time.perf_counter()
+            k = 0
+            lib_submit = srv.submit_raw
+            while True:
+                t += rng.exponential(threads_n / rate)
+                now = time.perf_counter()
+                if t > stop_at:
+                    break
+                if t > now:
+                    time.sleep(max(0.0, t - now - 50e-6))
+                    while time.perf_counter() < t:
+                        pass
+                w = int(rng.integers(0, 3))
+                sel = pool[w][k % 16]
+                out = outs[w][(tid * 512 + k) % 4096]
+                rc, tk = lib_submit(ids[w], sel.ctypes.data, out.ctypes.data)
+                if rc == 0:
+                    pending[tid].append(tk)
+                else:
+                    rejected[tid] += 1
+                k += 1
+
+        ths = [threading.Thread(target=submitter, args=(i,)) for i in range(threads_n)]
+        srv.stats(reset=True)
+        for th in ths:
+            th.start()
+        for th in ths:
+            th.join()
+        for lst in pending:
+            for tk in lst:
+                srv.wait(tk, 60000)
+        st = srv.stats()
+        srv.close()
+        hist = {f"{1 << i}-{(2 << i) - 1}": c for i, c in enumerate(st["batch_hist"]) if c}
+        rec = {"offered_qps": rate, "achieved_qps": st["completed"] / args.serve_seconds,
+               "completed": st["completed"], "rejected": st["rejected"] + sum(rejected),
+               "p50_ms": st["p50_us"] / 1e3, "p99_ms": st["p99_us"] / 1e3, "mean_ms": st["mean_us"] / 1e3,
+               "batches": st["batches"], "batch_hist": hist, "max_inflight": st["max_inflight"],
+               "h2d_GBps": st["h2d_bytes"] / args.serve_seconds / 1e9}
+        log(f"serve rate {rate}: {json.dumps(rec)}")
+        results.append(rec)
+    for d in dbs:
+        d.free()
+    ctx.close()
+    return results
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +239,15 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="use the default kernel plan")
     ap.add_argument("--cpu-sample", type=int, default=2, help="oracle queries for cpu_baseline (0 = skip)")
     ap.add_argument("--no-single", action="store_true", help="skip the single-query pass")
+    ap.add_argument("--serve", action="store_true", help="run the serving sweep (three resident DBs) instead")
+    ap.add_argument("--serve-rates", default="1000,2000,5000,10000,20000,50000")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-threads", type=int, default=8)
+    ap.add_argument("--serve-qmax", type=int, default=64)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-wait-us", type=int, default=200)
+    ap.add_argument("--calib-copy-gib", type=int, default=0,
+                    help="first run a plain device copy of this many GiB, 3 times (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -147,6 +260,28 @@ def main():
 
     import synth
     import paper_2509_06514_amd as pir
+
+    if args.serve:
+        res = serve_bench(args)
+        print(json.dumps({"metric": "serving p50/p99 latency vs offered load (3 resident DBs)",
+                          "unit": "ms", "data": "synthetic",
+                          "config": {"dbs": [{"n_records": n, "record_bytes": r} for n, r in SERVE_DBS],
+                                     "q_max": args.serve_qmax, "slots": args.serve_slots,
+                                     "max_wait_us": args.serve_wait_us, "seconds_per_rate": args.serve_seconds},
+                          "rates": res}), flush=True)
+        return
+
+    if args.calib_copy_gib > 0:
+        # a plain copy kernel of known size: reads and writes calib_copy_gib GiB per launch
+        nbytes = args.calib_copy_gib << 30
+        a = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0").fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy: 3 x {nbytes} bytes")
+        del a, b
 
     n, r, q = CONFIGS[args.config]
     log(f"config {args.config}: N={n} R={r} Q={q}")
@@ -208,7 +343,7 @@ def main():
             "db_gbs_scanned": n * r / (ms1 / 1e3) / 1e9,
             "latency_ms": {"p50": percentile(per_1, 0.5), "p99": percentile(per_1, 0.99)},
             "cfg": cfg_1.as_dict(),
-            "roofline": roofline_for(cfg_1.variant, n, r, 1, s1_avg, load_traffic(args.config, 1)),
+            "roofline": roofline_for(cfg_1.variant, n, r, 1, s1_avg, load_traffic(args.config, 1, cfg_1, r)),
         }
         log(f"Q=1: {ms1:.3f} ms/query, {single['db_gbs_scanned']:.0f} GB/s scanned, stage1 avg {s1_avg:.3f} ms")
 
@@ -235,7 +370,7 @@ def main():
         "db_gbs_scanned": n * r / (ms_step / 1e3) / 1e9,
         "latency_ms": {"p50": percentile(per_q, 0.5), "p99": percentile(per_q, 0.99)},
         "stage_ms": {"stage1_avg": s1q, "stage2_avg": tq["stage2_ms"] / max(1, tq["stage2_launches"])},
-        "roofline": roofline_for(cfg_q.variant, n, r, q, s1q, load_traffic(args.config, q)),
+        "roofline": roofline_for(cfg_q.variant, n, r, q, s1q, load_traffic(args.config, q, cfg_q, r)),
     }
     if single is not None:
         result["single_query"] = single
