@@ -79,7 +79,8 @@ int pir_ctx_destroy(pir_ctx* ctx);
  * HBM.  The caller may free `records` on return; the library owns the device
  * copy until pir_db_free.  The device copy is stored bit-sliced: each block
  * of 32 consecutive records becomes 8*R 32-bit words, word b holding bit b of
- * the 32 records (record 32*blk+i at bit i), with records past N zero.
+ * the 32 records, with records past N zero.  Record 32*blk+i sits at bit i,
+ * except that inside every 4-bit group records 4n and 4n+2 trade places.
  * Errors: PIR_E_INVAL (NULL, N = 0, R = 0, N*R overflow), PIR_E_NOMEM.
  */
 int pir_db_load(pir_ctx* ctx, const void* records, uint64_t n_records, uint32_t record_bytes,
@@ -148,7 +149,8 @@ int pir_dpxor_batch_async(pir_db* db, const void* d_sel, uint64_t sel_stride, ui
 typedef struct pir_kernel_cfg {
     uint32_t variant; /* PIR_VARIANT_* */
     uint32_t q_tile;  /* queries per workgroup tile (variant-specific; 0 = default) */
-    uint32_t unroll;  /* blocks per wave iteration (0 = default) */
+    uint32_t unroll;  /* VALU: blocks per wave iteration; MFMA: 1 = register pipeline,
+                         3/4/6 = LDS ring of that many stages (0 = default) */
     uint32_t groups;  /* record groups = partial results per query (0 = default) */
 } pir_kernel_cfg;
 

@@ -25,6 +25,8 @@ HIPCC_FLAGS = [
     "-Wno-unused-result",
     # packed fp32 VALU forms are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core accumulators live in ordinary VGPRs (no AGPR copies per step)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     f"-I{INCLUDE}",
     f"-I{CSRC}",
 ]

@@ -13,7 +13,8 @@ namespace pir {
 //
 // Records are grouped in blocks of 32.  Block blk is 8*R 32-bit words; word b
 // holds bit b of the 32 records (bit b of a record = bit (b & 7) of byte
-// b >> 3; record 32*blk + i sits at bit i of the word).  A block is 32*R
+// b >> 3; record 32*blk + i sits at bit i of the word, except that inside each
+// 4-bit group records 4n and 4n+2 trade places; see nib_swap02).  A block is 32*R
 // bytes = 2*R 16-byte chunks.  Scans read whole chunks, one per lane.
 //
 //  - R >= 32 ("wide"): a wave covers 64 chunks (1 KiB, 256 bit columns) of one

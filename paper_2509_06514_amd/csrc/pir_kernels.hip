@@ -65,6 +65,16 @@ __device__ __forceinline__ void sel_xor(u32x4& acc, const u32x4& d, uint32_t s) 
     acc.w = xor_and(acc.w, d.w, s);
 }
 
+// Stored word order.  Inside every nibble of a bit-sliced word the records
+// 4n and 4n+2 trade places (an involution): stored bit 4n+2 is record 4n and
+// stored bit 4n is record 4n+2.  This lets the matrix-core spread of a
+// database word use masks for three of its four parts (spread_fp4_b).  A
+// selection word, which arrives in record order, is brought to stored order
+// with the same swap before it meets a stored word bit for bit.
+__device__ __forceinline__ uint32_t nib_swap02(uint32_t x) {
+    return (x & 0xAAAAAAAAu) | ((x & 0x11111111u) << 2) | ((x >> 2) & 0x11111111u);
+}
+
 // Workgroup -> (record group, column tile, query tile).  Workgroups are
 // dispatched round-robin over the 8 XCDs; consecutive workgroups on one XCD
 // get the column/query tiles of the same record group, so the selection
@@ -137,10 +147,10 @@ k_stage1_valu(const u32x4* __restrict__ db, const uint32_t* __restrict__ sel,
                 uint64_t blk = (u + k) * p.bpw + bi;
                 blk = blk < p.nb ? blk : p.nb - 1;  // padding blocks are zero: any word will do
 #pragma unroll
-                for (int q = 0; q < QT; ++q) sel_xor(acc[q], d[k], srow[q][blk]);
+                for (int q = 0; q < QT; ++q) sel_xor(acc[q], d[k], nib_swap02(srow[q][blk]));
             } else {
 #pragma unroll
-                for (int q = 0; q < QT; ++q) sel_xor(acc[q], d[k], srow[q][u + k]);
+                for (int q = 0; q < QT; ++q) sel_xor(acc[q], d[k], nib_swap02(srow[q][u + k]));
             }
         }
     }
@@ -151,10 +161,10 @@ k_stage1_valu(const u32x4* __restrict__ db, const uint32_t* __restrict__ sel,
             uint64_t blk = (u + k) * p.bpw + bi;
             blk = blk < p.nb ? blk : p.nb - 1;
 #pragma unroll
-            for (int q = 0; q < QT; ++q) sel_xor(acc[q], dk, srow[q][blk]);
+            for (int q = 0; q < QT; ++q) sel_xor(acc[q], dk, nib_swap02(srow[q][blk]));
         } else {
 #pragma unroll
-            for (int q = 0; q < QT; ++q) sel_xor(acc[q], dk, srow[q][u + k]);
+            for (int q = 0; q < QT; ++q) sel_xor(acc[q], dk, nib_swap02(srow[q][u + k]));
         }
     }
 
@@ -223,14 +233,34 @@ __device__ __forceinline__ void wait_vmcnt() {
 // side of it.
 __device__ __forceinline__ void wg_barrier() { asm volatile("s_barrier" ::: "memory"); }
 
-// 32 bits -> 32 E2M1 values (1.0 = 0b0010 where the bit is set): dword t,
-// nibble n holds bit 4n + t.
-__device__ __forceinline__ i32x8 spread_fp4(uint32_t w) {
+// 32 records of one word -> 32 E2M1 values, element (dword t, nibble n) =
+// record 4n + t.  The selection side (A, record order) and the database side
+// (B, stored order) use reciprocal values so that every product of two set
+// bits is exactly 1.0:
+//   t:    0     1     2     3
+//   A:   0.5   1.0   2.0   2.0     (E2M1 0b0001, 0b0010, 0b0100, 0b0100)
+//   B:   2.0   1.0   0.5   0.5
+// Each record is taken where it already sits in its nibble when that position
+// carries the wanted value (a mask only); nibble bit 3 would be the sign, so
+// record 4n+3 is shifted down on both sides.
+__device__ __forceinline__ i32x8 spread_fp4_a(uint32_t w) {  // w in record order
     i32x8 r;
-    r[0] = (int32_t)((w << 1) & 0x22222222u);
-    r[1] = (int32_t)(w & 0x22222222u);
-    r[2] = (int32_t)((w >> 1) & 0x22222222u);
-    r[3] = (int32_t)((w >> 2) & 0x22222222u);
+    r[0] = (int32_t)(w & 0x11111111u);          // record 4n   at bit 0: 0.5
+    r[1] = (int32_t)(w & 0x22222222u);          // record 4n+1 at bit 1: 1.0
+    r[2] = (int32_t)(w & 0x44444444u);          // record 4n+2 at bit 2: 2.0
+    r[3] = (int32_t)((w >> 1) & 0x44444444u);   // record 4n+3 to bit 2: 2.0
+    r[4] = 0;
+    r[5] = 0;
+    r[6] = 0;
+    r[7] = 0;
+    return r;
+}
+__device__ __forceinline__ i32x8 spread_fp4_b(uint32_t w) {  // w in stored order
+    i32x8 r;
+    r[0] = (int32_t)(w & 0x44444444u);          // record 4n   stored at bit 2: 2.0
+    r[1] = (int32_t)(w & 0x22222222u);          // record 4n+1 at bit 1: 1.0
+    r[2] = (int32_t)(w & 0x11111111u);          // record 4n+2 stored at bit 0: 0.5
+    r[3] = (int32_t)((w >> 3) & 0x11111111u);   // record 4n+3 to bit 0: 0.5
     r[4] = 0;
     r[5] = 0;
     r[6] = 0;
@@ -238,9 +268,11 @@ __device__ __forceinline__ i32x8 spread_fp4(uint32_t w) {
     return r;
 }
 
-// 32 bits -> 32 int8 0/1 values in two 16-element halves: dword t, byte m
-// holds bit 8m + t (half 0: t = 0..3, half 1: t = 4..7).
-__device__ __forceinline__ void spread_i8(uint32_t w, i32x4& lo, i32x4& hi) {
+// 32 records -> 32 int8 0/1 values in two 16-element halves: dword t, byte
+// m holds record 8m + t (half 0: t = 0..3, half 1: t = 4..7).  Record
+// 8m + t sits at bit 8m + t of a selection word; in a stored database word
+// records 8m, 8m+2 (and 8m+4, 8m+6) trade places.
+__device__ __forceinline__ void spread_i8(uint32_t w, i32x4& lo, i32x4& hi) {  // record order
     lo[0] = (int32_t)(w & 0x01010101u);
     lo[1] = (int32_t)((w >> 1) & 0x01010101u);
     lo[2] = (int32_t)((w >> 2) & 0x01010101u);
@@ -248,6 +280,16 @@ __device__ __forceinline__ void spread_i8(uint32_t w, i32x4& lo, i32x4& hi) {
     hi[0] = (int32_t)((w >> 4) & 0x01010101u);
     hi[1] = (int32_t)((w >> 5) & 0x01010101u);
     hi[2] = (int32_t)((w >> 6) & 0x01010101u);
+    hi[3] = (int32_t)((w >> 7) & 0x01010101u);
+}
+__device__ __forceinline__ void spread_i8_stored(uint32_t w, i32x4& lo, i32x4& hi) {  // stored order
+    lo[0] = (int32_t)((w >> 2) & 0x01010101u);
+    lo[1] = (int32_t)((w >> 1) & 0x01010101u);
+    lo[2] = (int32_t)(w & 0x01010101u);
+    lo[3] = (int32_t)((w >> 3) & 0x01010101u);
+    hi[0] = (int32_t)((w >> 6) & 0x01010101u);
+    hi[1] = (int32_t)((w >> 5) & 0x01010101u);
+    hi[2] = (int32_t)((w >> 4) & 0x01010101u);
     hi[3] = (int32_t)((w >> 7) & 0x01010101u);
 }
 
@@ -329,10 +371,10 @@ k_stage1_mfma(const uint32_t* __restrict__ db, const uint32_t* __restrict__ sel,
             if (F4) {
                 i32x8 bx[4];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) bx[t] = spread_fp4(st.bw[s][t]);
+                for (int t = 0; t < 4; ++t) bx[t] = spread_fp4_b(st.bw[s][t]);
 #pragma unroll
                 for (int rt = 0; rt < MT; ++rt) {
-                    const i32x8 ax = spread_fp4(qok[rt] ? st.aw[rt][s] : 0u);
+                    const i32x8 ax = spread_fp4_a(st.aw[rt][s]);
 #pragma unroll
                     for (int t = 0; t < 4; ++t)
                         acc[rt][t] = (acc_t)__builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
@@ -341,11 +383,11 @@ k_stage1_mfma(const uint32_t* __restrict__ db, const uint32_t* __restrict__ sel,
             } else {
                 i32x4 blo[4], bhi[4];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) spread_i8(st.bw[s][t], blo[t], bhi[t]);
+                for (int t = 0; t < 4; ++t) spread_i8_stored(st.bw[s][t], blo[t], bhi[t]);
 #pragma unroll
                 for (int rt = 0; rt < MT; ++rt) {
                     i32x4 alo, ahi;
-                    spread_i8(qok[rt] ? st.aw[rt][s] : 0u, alo, ahi);
+                    spread_i8(st.aw[rt][s], alo, ahi);
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
                         acc[rt][t] = (acc_t)__builtin_amdgcn_mfma_i32_16x16x64_i8(alo, blo[t], (i32x4)acc[rt][t], 0, 0, 0);
@@ -455,9 +497,18 @@ __device__ __forceinline__ void lds_read_step(uint32_t b, uint32_t a, u32x4 (&bw
 // chunks and selection words into LDS while the current K-step runs on the
 // matrix cores, so the bytes in flight do not cost registers.  Per K-step a
 // stage holds the workgroup's 16 blocks x 256 bit columns (16 KiB) and its
-// 16*MT query rows x 16 selection words.  Each wave waits for its own loads
-// of the step (vmcnt) and a barrier makes every wave's part visible; the
-// same barrier tells the wave that refills a stage that it has been read.
+// 16*MT query rows x 16 selection words; the ring lives in dynamic LDS
+// (up to 160 KiB on gfx950).  Each wave waits for its own loads of the step
+// (vmcnt) and a barrier makes every wave's part visible; the same barrier
+// tells the wave that refills a stage that everyone has read it.  Stage
+// operands are read by lds_read_step, whose own lgkmcnt wait completes them.
+constexpr uint32_t kStageDbBytes = 16 * 256 * 4;
+
+template <int MT>
+__host__ __device__ constexpr uint32_t ring_bytes(int stages) {
+    return (uint32_t)stages * (kStageDbBytes + 16u * MT * 16u * 4u);
+}
+
 template <int MT, bool F4, int S>
 __global__ void __launch_bounds__(kThreads)
 k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ sel,
@@ -465,19 +516,11 @@ k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
     typedef typename MfmaAcc<F4>::type acc_t;
     constexpr int QT = 16 * MT;
     constexpr int kLoadsPerStep = 4 + MT;  // per wave: 4 database chunks + MT selection rows-of-4
-    static_assert(S == 3, "three ring stages");
-    // one LDS object per stage: accesses to different stages are then known
-    // not to alias, so reads of one stage do not wait for loads into another
-    __shared__ __attribute__((aligned(16))) uint32_t lds_db0[16][256];
-    __shared__ __attribute__((aligned(16))) uint32_t lds_db1[16][256];
-    __shared__ __attribute__((aligned(16))) uint32_t lds_db2[16][256];
-    __shared__ __attribute__((aligned(16))) uint32_t lds_sel0[QT][16];
-    __shared__ __attribute__((aligned(16))) uint32_t lds_sel1[QT][16];
-    __shared__ __attribute__((aligned(16))) uint32_t lds_sel2[QT][16];
-    // (a macro, not a lambda: a lambda returning these arrays keeps clang
-    // from emitting the kernel's host launch stub)
-#define PIR_STAGE_DB(slot) ((slot) == 0 ? lds_db0 : ((slot) == 1 ? lds_db1 : lds_db2))
-#define PIR_STAGE_SEL(slot) ((slot) == 0 ? lds_sel0 : ((slot) == 1 ? lds_sel1 : lds_sel2))
+    constexpr uint32_t kStageSelBytes = QT * 16 * 4;
+    static_assert(S >= 3 && S <= 8, "ring stages");
+    extern __shared__ __attribute__((aligned(16))) uint8_t pir_ring[];
+    uint8_t* const ring_db = pir_ring;                        // S x [16 blocks][256 words]
+    uint8_t* const ring_sel = pir_ring + S * kStageDbBytes;  // S x [QT rows][16 words]
 
     uint32_t group, ct, qt;
     if (!decode_block(p.groups, p.n_ct, p.n_qt, group, ct, qt)) return;
@@ -488,13 +531,13 @@ k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
     const uint32_t q0 = qt * QT;
     const uint64_t block_words = 8ull * p.R;
 
-    bool qok[MT];
-#pragma unroll
-    for (int rt = 0; rt < MT; ++rt) qok[rt] = q0 + 16 * rt + j < p.q_total;
-
-    // loader geometry: database chunk of lane l = words 4l..4l+3 of the tile;
-    // selection row (4i + l/16), word l%16 of the step
-    const uint32_t* db_src = db + ct * 256 + 4 * lane;
+    // Query rows past q_total read row q0 (a valid row) and are never
+    // written out, so the scan needs no per-step masking.
+    //
+    // loader geometry: database chunk of lane l = words 4l..4l+3 of the tile
+    // (wave w loads blocks w, w+4, w+8, w+12 of the step); selection row
+    // 4*(w + 4i) + l/16, word l%16 of the step
+    const uint32_t* db_tile = db + ct * 256;  // wave-uniform base; lanes add 16 B each
     const uint32_t* sel_src[MT];
 #pragma unroll
     for (int i = 0; i < MT; ++i) {
@@ -502,15 +545,18 @@ k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
         const uint32_t q = q0 + row < p.q_total ? q0 + row : q0;
         sel_src[i] = sel + (uint64_t)q * p.stride_words + (lane & 15);
     }
-    auto issue = [&](uint64_t kb, int slot) {
+    auto issue = [&](uint64_t kb, uint32_t slot) {
+        uint8_t* dst_db = ring_db + slot * kStageDbBytes;
+        uint8_t* dst_sel = ring_sel + slot * kStageSelBytes;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const uint32_t b = 4 * i + wave;
-            __builtin_amdgcn_global_load_lds(db_src + (kb + b) * block_words, &PIR_STAGE_DB(slot)[b][0], 16, 0, 0);
+            const uint32_t* base = db_tile + (kb + b) * block_words;  // uniform
+            __builtin_amdgcn_global_load_lds(base + 4 * lane, dst_db + b * 1024, 16, 0, 0);
         }
 #pragma unroll
         for (int i = 0; i < MT; ++i)
-            __builtin_amdgcn_global_load_lds(sel_src[i] + kb, &PIR_STAGE_SEL(slot)[4 * (wave + 4 * i)][0], 4, 0, 0);
+            __builtin_amdgcn_global_load_lds(sel_src[i] + kb, dst_sel + (wave + 4 * i) * 256, 4, 0, 0);
     };
 
     acc_t acc[MT][4];
@@ -525,10 +571,10 @@ k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
             if (F4) {
                 i32x8 bx[4];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) bx[t] = spread_fp4(bw[s][t]);
+                for (int t = 0; t < 4; ++t) bx[t] = spread_fp4_b(bw[s][t]);
 #pragma unroll
                 for (int rt = 0; rt < MT; ++rt) {
-                    const i32x8 ax = spread_fp4(qok[rt] ? aw4[rt][s] : 0u);
+                    const i32x8 ax = spread_fp4_a(aw4[rt][s]);
 #pragma unroll
                     for (int t = 0; t < 4; ++t)
                         acc[rt][t] = (acc_t)__builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
@@ -537,11 +583,11 @@ k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
             } else {
                 i32x4 blo[4], bhi[4];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) spread_i8(bw[s][t], blo[t], bhi[t]);
+                for (int t = 0; t < 4; ++t) spread_i8_stored(bw[s][t], blo[t], bhi[t]);
 #pragma unroll
                 for (int rt = 0; rt < MT; ++rt) {
                     i32x4 alo, ahi;
-                    spread_i8(qok[rt] ? aw4[rt][s] : 0u, alo, ahi);
+                    spread_i8(aw4[rt][s], alo, ahi);
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
                         acc[rt][t] = (acc_t)__builtin_amdgcn_mfma_i32_16x16x64_i8(alo, blo[t], (i32x4)acc[rt][t], 0, 0, 0);
@@ -551,11 +597,12 @@ k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
             }
         }
     };
-    auto compute_slot = [&](int slot) {
+    // this lane's operand addresses inside stage 0; stage k adds k * stage size
+    const uint32_t rd_db = (uint32_t)(uintptr_t)(ring_db + (4 * g) * 1024 + (64 * wave + 4 * j) * 4);
+    const uint32_t rd_sel = (uint32_t)(uintptr_t)(ring_sel + j * 64 + (4 * g) * 4);
+    auto compute_slot = [&](uint32_t slot) {
         u32x4 bw[4], aw4[MT];
-        const uint32_t b = (uint32_t)(uintptr_t)&PIR_STAGE_DB(slot)[4 * g][64 * wave + 4 * j];
-        const uint32_t a = (uint32_t)(uintptr_t)&PIR_STAGE_SEL(slot)[j][4 * g];
-        lds_read_step<MT>(b, a, bw, aw4);
+        lds_read_step<MT>(rd_db + slot * kStageDbBytes, rd_sel + slot * kStageSelBytes, bw, aw4);
         mma(bw, aw4);
     };
 
@@ -569,35 +616,28 @@ k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
         if ((uint64_t)k < nsteps) issue(b_begin + k * kMfmaBlocksPerStep, k);
 
     uint64_t k = 0;
-    // Steady state: every step issues the load of step k+S-1, so the body is
-    // straight-line code (one basic block) and the per-step scheduling
-    // barriers hold.  Unrolled by S so every stage index is a constant.
-    for (; k + 2 * S - 2 < nsteps; k += S) {
-#pragma unroll
-        for (int u = 0; u < S; ++u) {
-            wait_vmcnt<(S - 2) * kLoadsPerStep>();  // own loads of step k+u have landed
-            wg_barrier();                            // ... and everyone's; stage u-1 is free
-            issue(b_begin + (k + u + S - 1) * kMfmaBlocksPerStep, (u + S - 1) % S);
-            compute_slot(u);
-            __builtin_amdgcn_sched_barrier(0);       // keep this step's matrix work here
-        }
+    uint32_t slot = 0, fill = S - 1;  // stage of step k, stage that step k+S-1 loads into
+    // Steady state: every step issues the load of step k+S-1; straight-line
+    // body so the per-step scheduling barrier holds.
+    for (; k + S - 1 < nsteps; ++k) {
+        wait_vmcnt<(S - 2) * kLoadsPerStep>();  // own loads of step k have landed
+        wg_barrier();                            // ... and everyone's; stage `fill` has been read
+        issue(b_begin + (k + S - 1) * kMfmaBlocksPerStep, fill);
+        compute_slot(slot);
+        __builtin_amdgcn_sched_barrier(0);       // keep this step's matrix work here
+        slot = slot + 1 == S ? 0 : slot + 1;
+        fill = fill + 1 == S ? 0 : fill + 1;
     }
-    // last steps (fewer than 2S-1): same ring, with bounds
-    for (; k < nsteps; k += S) {
-#pragma unroll
-        for (int u = 0; u < S; ++u) {
-            if (k + u < nsteps) {
-                wait_vmcnt<0>();
-                wg_barrier();
-                if (k + u + S - 1 < nsteps) issue(b_begin + (k + u + S - 1) * kMfmaBlocksPerStep, (u + S - 1) % S);
-                compute_slot(u);
-            }
-        }
+    // last S-1 steps: everything is already in flight
+    wait_vmcnt<0>();
+    wg_barrier();
+    for (; k < nsteps; ++k) {
+        compute_slot(slot);
+        slot = slot + 1 == S ? 0 : slot + 1;
     }
-    k = nsteps;
 
     // ragged tail (fewer than 16 blocks) straight from memory
-    const uint64_t kb = b_begin + k * kMfmaBlocksPerStep;
+    const uint64_t kb = b_begin + nsteps * kMfmaBlocksPerStep;
     if (kb < b_end) {
         const u32x4* dl = reinterpret_cast<const u32x4*>(db + ct * 256 + wave * 64 + 4 * j);
         u32x4 bw[4], aw4[MT];
@@ -633,9 +673,6 @@ k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
             }
         }
 }
-
-#undef PIR_STAGE_DB
-#undef PIR_STAGE_SEL
 
 // Stage 2: out[q][m] = XOR over groups of partials[g][q][m].  Each workgroup
 // owns `wpb` consecutive 32-bit words of the [q][rpad] result and splits the
@@ -696,7 +733,7 @@ k_slice(const uint8_t* __restrict__ src, uint64_t nrec, uint32_t R, uint32_t* __
             if ((lane & 7) == t) w = (lane & 8) ? (uint32_t)(m >> 32) : (uint32_t)m;
         }
         const uint32_t col = 8 * c + (lane & 15);
-        if (lane < 16 && col < 8 * R) out[col] = w;
+        if (lane < 16 && col < 8 * R) out[col] = nib_swap02(w);  // stored order
     }
 }
 
@@ -713,7 +750,7 @@ k_unslice(const uint32_t* __restrict__ src, uint64_t nblk, uint32_t R, uint8_t* 
     uint8_t* rp = dst + rec * R;
     for (uint32_t c = 0; c < R; ++c) {
         uint32_t byte = 0;
-        for (uint32_t t = 0; t < 8; ++t) byte |= ((in[8 * c + t] >> lane) & 1u) << t;
+        for (uint32_t t = 0; t < 8; ++t) byte |= ((nib_swap02(in[8 * c + t]) >> lane) & 1u) << t;
         rp[c] = (uint8_t)byte;
     }
 }
@@ -805,10 +842,26 @@ hipError_t launch_unslice(const Geometry& g, const uint32_t* src_block0, uint64_
 bool mfma_supported(uint32_t variant, const Geometry& g, uint32_t qt, uint32_t unroll) {
     if (variant != PIR_VARIANT_MFMA_F4 && variant != PIR_VARIANT_MFMA_I8) return false;
     if (g.R % 32 != 0) return false;  // whole 256-column tiles
-    // unroll selects the pipeline: 4 = one K-step ahead in registers,
-    // 8 = two K-steps ahead through a 3-stage LDS ring
-    if (unroll != 4 && unroll != 8) return false;
+    // unroll selects the pipeline: 1 = one K-step ahead in registers;
+    // 3, 4, 6 = an LDS ring of that many stages (that many minus one K-steps
+    // in flight), within the 160 KiB of LDS a workgroup may use
+    if (unroll != 1 && unroll != 3 && unroll != 4 && unroll != 6) return false;
     return qt == 16 || qt == 32 || qt == 64;
+}
+
+template <int MT, bool F4, int S>
+static hipError_t launch_ring(dim3 grid, hipStream_t s, const uint32_t* db, const uint32_t* sel, uint8_t* partials,
+                              const Stage1Params& p) {
+    constexpr uint32_t bytes = ring_bytes<MT>(S);
+    static bool attr_set = false;  // the dynamic-LDS limit is raised once per instance
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage1_mfma_lds<MT, F4, S>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_stage1_mfma_lds<MT, F4, S>), grid, dim3(kThreads), bytes, s, db, sel, partials, p);
+    return hipGetLastError();
 }
 
 template <int MT, bool F4>
@@ -830,14 +883,16 @@ static hipError_t launch_mfma_t(const Geometry& g, const Plan& pl, const void* d
     p.R = g.R;
     p.rpad = g.rpad;
     const uint32_t total = pl.groups * g.n_ct * pl.n_qt;
-    const uint32_t grid = (total + 7) / 8 * 8;
-    if (pl.unroll == 8)
-        hipLaunchKernelGGL((k_stage1_mfma_lds<MT, F4, 3>), dim3(grid), dim3(kThreads), 0, s, (const uint32_t*)db,
-                           sel, partials, p);
-    else
-        hipLaunchKernelGGL((k_stage1_mfma<MT, F4>), dim3(grid), dim3(kThreads), 0, s, (const uint32_t*)db, sel,
-                           partials, p);
-    return hipGetLastError();
+    const dim3 grid((total + 7) / 8 * 8);
+    const uint32_t* d = (const uint32_t*)db;
+    switch (pl.unroll) {
+        case 3: return launch_ring<MT, F4, 3>(grid, s, d, sel, partials, p);
+        case 4: return launch_ring<MT, F4, 4>(grid, s, d, sel, partials, p);
+        case 6: return launch_ring<MT, F4, 6>(grid, s, d, sel, partials, p);
+        default:
+            hipLaunchKernelGGL((k_stage1_mfma<MT, F4>), grid, dim3(kThreads), 0, s, d, sel, partials, p);
+            return hipGetLastError();
+    }
 }
 
 hipError_t launch_stage1_mfma(const Geometry& g, const Plan& p, const void* db, const uint32_t* sel,

@@ -106,7 +106,7 @@ int finish_plan(const Geometry& g, uint32_t q, Plan& p) {
             return fail(PIR_E_INVAL, "no VALU kernel for q_tile=%u unroll=%u", p.qt, p.unroll);
     } else if (p.variant == PIR_VARIANT_MFMA_I8 || p.variant == PIR_VARIANT_MFMA_F4) {
         if (p.qt == 0) p.qt = q <= 16 ? 16 : (q <= 32 ? 32 : 64);
-        if (p.unroll == 0) p.unroll = 4;
+        if (p.unroll == 0) p.unroll = 4;  // LDS ring of 4 stages
         if (!mfma_supported(p.variant, g, p.qt, p.unroll))
             return fail(PIR_E_INVAL, "no MFMA kernel (variant %u) for R=%u q_tile=%u unroll=%u",
                         p.variant, g.R, p.qt, p.unroll);
@@ -649,7 +649,7 @@ int pir_tune(pir_db* d, uint32_t q, pir_kernel_cfg* out) {
     }
     for (uint32_t v : {PIR_VARIANT_MFMA_I8, PIR_VARIANT_MFMA_F4})
         for (uint32_t qt : {16u, 32u, 64u})
-            for (uint32_t u : {4u, 8u})
+            for (uint32_t u : {1u, 3u, 4u, 6u})
                 if (q >= 8 && qt <= qmax_tile && mfma_supported(v, g, qt, u)) cands.push_back({v, qt, u, 0});
     // grid variants of each: the default record-group count, half and double
     std::vector<pir_kernel_cfg> all;

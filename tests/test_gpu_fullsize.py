@@ -66,13 +66,13 @@ def test_c4_tuned_plan_matches_oracle_rows(c4, q):
 def test_c4_variants_agree(c4, q):
     # bitwise select-XOR, int8 matrix cores and fp4 matrix cores: identical rows
     dbh, db, sel, d_sel, stride, rows = c4
-    ref = _run(db, d_sel, stride, q, pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 8, 0))
+    ref = _run(db, d_sel, stride, q, pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 4, 0))
     for i, want in rows.items():
         if i < q:
             assert np.array_equal(ref[i], want)
-    for cfg in (pir.KernelCfg(pir.PIR_VARIANT_MFMA_I8, 64, 8, 0),
-                pir.KernelCfg(pir.PIR_VARIANT_MFMA_I8, 32, 4, 0),
-                pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 32, 4, 0),
+    for cfg in (pir.KernelCfg(pir.PIR_VARIANT_MFMA_I8, 64, 6, 0),
+                pir.KernelCfg(pir.PIR_VARIANT_MFMA_I8, 32, 1, 0),
+                pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 32, 3, 0),
                 pir.KernelCfg(pir.PIR_VARIANT_VALU, 16, 4, 0)):
         got = _run(db, d_sel, stride, q, cfg)
         assert np.array_equal(got, ref), cfg

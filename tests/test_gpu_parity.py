@@ -205,7 +205,7 @@ def test_mfma_variants(ctx, variant, n, r):
     for q in qs:
         d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
         for qt in (16, 32, 64):
-            for unroll in (4, 8):  # register pipeline, LDS ring
+            for unroll in (1, 3, 4, 6):  # register pipeline, LDS rings of 3/4/6 stages
                 for groups in (0, 3, 1):
                     d_out.fill_(0xEE)
                     db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride,
@@ -231,7 +231,7 @@ def test_mfma_counts_exact_on_large_group(ctx, variant):
     d_sel = torch.from_numpy(host).to("cuda:0")
     d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
     want3 = oracle.dpxor(dbh, rnd[0])
-    for unroll in (4, 8):
+    for unroll in (1, 3, 6):
         d_out.fill_(0)
         db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride, cfg=pir.KernelCfg(variant, 16, unroll, 1))
         torch.cuda.synchronize()
