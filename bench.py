@@ -55,7 +55,9 @@ def kernel_name(cfg, r):
     mt = cfg.q_tile // 16
     f4 = "true" if cfg.variant == 3 else "false"
     if cfg.unroll in (3, 4, 6):  # LDS ring of that many stages
-        return f"k_stage1_mfma_lds<{mt}, {f4}, {cfg.unroll}>"
+        return f"k_stage1_mfma_lds<{mt}, {f4}, {cfg.unroll}, false>"
+    if cfg.unroll == 7:  # 3-stage ring, selection operand spread once per workgroup
+        return f"k_stage1_mfma_lds<{mt}, {f4}, 3, true>"
     return f"k_stage1_mfma<{mt}, {f4}>"
 
 

@@ -492,6 +492,56 @@ __device__ __forceinline__ void lds_read_step(uint32_t b, uint32_t a, u32x4 (&bw
     }
 }
 
+// Shared-spread helpers (each asm block waits for its own LDS traffic).
+// Four database chunks at b + 0/1/2/3 KiB and one selection quad at a.
+__device__ __forceinline__ void lds_read_b4a1(uint32_t b, uint32_t a, u32x4 (&bw)[4], u32x4& aw) {
+    asm volatile(
+        "ds_read_b128 %0, %5\n\t"
+        "ds_read_b128 %1, %5 offset:1024\n\t"
+        "ds_read_b128 %2, %5 offset:2048\n\t"
+        "ds_read_b128 %3, %5 offset:3072\n\t"
+        "ds_read_b128 %4, %6\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(bw[0]), "=&v"(bw[1]), "=&v"(bw[2]), "=&v"(bw[3]), "=&v"(aw)
+        : "v"(b), "v"(a));
+}
+// Four 16-byte values to w + 0/1/2/3 KiB.
+__device__ __forceinline__ void lds_write_4(uint32_t w, const u32x4 (&v)[4]) {
+    asm volatile(
+        "ds_write_b128 %0, %1\n\t"
+        "ds_write_b128 %0, %2 offset:1024\n\t"
+        "ds_write_b128 %0, %3 offset:2048\n\t"
+        "ds_write_b128 %0, %4 offset:3072\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        :
+        : "v"(w), "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]));
+}
+// Sixteen 16-byte values from r + i KiB, i = 0..15.
+__device__ __forceinline__ void lds_read_16(uint32_t r, u32x4 (&v)[16]) {
+    asm volatile(
+        "ds_read_b128 %0, %16\n\t"
+        "ds_read_b128 %1, %16 offset:1024\n\t"
+        "ds_read_b128 %2, %16 offset:2048\n\t"
+        "ds_read_b128 %3, %16 offset:3072\n\t"
+        "ds_read_b128 %4, %16 offset:4096\n\t"
+        "ds_read_b128 %5, %16 offset:5120\n\t"
+        "ds_read_b128 %6, %16 offset:6144\n\t"
+        "ds_read_b128 %7, %16 offset:7168\n\t"
+        "ds_read_b128 %8, %16 offset:8192\n\t"
+        "ds_read_b128 %9, %16 offset:9216\n\t"
+        "ds_read_b128 %10, %16 offset:10240\n\t"
+        "ds_read_b128 %11, %16 offset:11264\n\t"
+        "ds_read_b128 %12, %16 offset:12288\n\t"
+        "ds_read_b128 %13, %16 offset:13312\n\t"
+        "ds_read_b128 %14, %16 offset:14336\n\t"
+        "ds_read_b128 %15, %16 offset:15360\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2]), "=&v"(v[3]), "=&v"(v[4]), "=&v"(v[5]), "=&v"(v[6]),
+          "=&v"(v[7]), "=&v"(v[8]), "=&v"(v[9]), "=&v"(v[10]), "=&v"(v[11]), "=&v"(v[12]), "=&v"(v[13]),
+          "=&v"(v[14]), "=&v"(v[15])
+        : "v"(r));
+}
+
 // Matrix-core scan with a multi-stage LDS ring.  Direct-to-LDS loads
 // (global_load_lds_dwordx4 / _dword) stream the next S-1 K-steps of database
 // chunks and selection words into LDS while the current K-step runs on the
@@ -509,7 +559,13 @@ __host__ __device__ constexpr uint32_t ring_bytes(int stages) {
     return (uint32_t)stages * (kStageDbBytes + 16u * MT * 16u * 4u);
 }
 
-template <int MT, bool F4, int S>
+//
+// With SA ("shared A"), the selection operand is spread once per workgroup
+// instead of once per wave: wave w spreads row tile w (its 16 queries) for
+// the step's four sub-steps and publishes the spread values through a
+// 16 KiB LDS buffer [row tile][sub-step][lane][16 B]; a second barrier per
+// step separates those writes from the reads.  (fp4, 64-query tiles.)
+template <int MT, bool F4, int S, bool SA>
 __global__ void __launch_bounds__(kThreads)
 k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ sel,
                   uint8_t* __restrict__ partials, Stage1Params p) {
@@ -518,9 +574,11 @@ k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
     constexpr int kLoadsPerStep = 4 + MT;  // per wave: 4 database chunks + MT selection rows-of-4
     constexpr uint32_t kStageSelBytes = QT * 16 * 4;
     static_assert(S >= 3 && S <= 8, "ring stages");
+    static_assert(!SA || (MT == 4 && F4), "shared spread: fp4, four row tiles");
     extern __shared__ __attribute__((aligned(16))) uint8_t pir_ring[];
     uint8_t* const ring_db = pir_ring;                        // S x [16 blocks][256 words]
     uint8_t* const ring_sel = pir_ring + S * kStageDbBytes;  // S x [QT rows][16 words]
+    uint8_t* const spread_a = ring_sel + S * kStageSelBytes;  // SA: [4 row tiles][4 sub-steps][64][16 B]
 
     uint32_t group, ct, qt;
     if (!decode_block(p.groups, p.n_ct, p.n_qt, group, ct, qt)) return;
@@ -600,10 +658,45 @@ k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
     // this lane's operand addresses inside stage 0; stage k adds k * stage size
     const uint32_t rd_db = (uint32_t)(uintptr_t)(ring_db + (4 * g) * 1024 + (64 * wave + 4 * j) * 4);
     const uint32_t rd_sel = (uint32_t)(uintptr_t)(ring_sel + j * 64 + (4 * g) * 4);
+    // SA: this wave's own selection quad (row 16*wave + j, words 4g..4g+3)
+    const uint32_t rd_own = (uint32_t)(uintptr_t)(ring_sel + (16 * wave + j) * 64 + (4 * g) * 4);
+    const uint32_t wr_spread = (uint32_t)(uintptr_t)(spread_a + (4 * wave) * 1024 + lane * 16);
+    const uint32_t rd_spread = (uint32_t)(uintptr_t)(spread_a + lane * 16);
     auto compute_slot = [&](uint32_t slot) {
-        u32x4 bw[4], aw4[MT];
-        lds_read_step<MT>(rd_db + slot * kStageDbBytes, rd_sel + slot * kStageSelBytes, bw, aw4);
-        mma(bw, aw4);
+        u32x4 bw[4];
+        if constexpr (SA) {
+            u32x4 own;
+            lds_read_b4a1(rd_db + slot * kStageDbBytes, rd_own + slot * kStageSelBytes, bw, own);
+            u32x4 sp[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const i32x8 x = spread_fp4_a(own[s]);
+                sp[s] = u32x4{(uint32_t)x[0], (uint32_t)x[1], (uint32_t)x[2], (uint32_t)x[3]};
+            }
+            lds_write_4(wr_spread, sp);
+            wg_barrier();  // every row tile's spread values are in LDS
+            u32x4 av[16];  // [row tile][sub-step]
+            lds_read_16(rd_spread, av);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                i32x8 bx[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) bx[t] = spread_fp4_b(bw[s][t]);
+#pragma unroll
+                for (int rt = 0; rt < MT; ++rt) {
+                    const u32x4 a4 = av[rt * 4 + s];
+                    const i32x8 ax = i32x8{(int32_t)a4[0], (int32_t)a4[1], (int32_t)a4[2], (int32_t)a4[3], 0, 0, 0, 0};
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        acc[rt][t] = (acc_t)__builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                            ax, bx[t], (f32x4)acc[rt][t], 4, 4, 0, 127, 0, 127);
+                }
+            }
+        } else {
+            u32x4 aw4[MT];
+            lds_read_step<MT>(rd_db + slot * kStageDbBytes, rd_sel + slot * kStageSelBytes, bw, aw4);
+            mma(bw, aw4);
+        }
     };
 
     const uint64_t b_begin = (uint64_t)group * p.units_per_group;
@@ -631,7 +724,8 @@ k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
     // last S-1 steps: everything is already in flight
     wait_vmcnt<0>();
     wg_barrier();
-    for (; k < nsteps; ++k) {
+    for (uint64_t k0 = k; k < nsteps; ++k) {
+        if (SA && k != k0) wg_barrier();  // the shared spread buffer has been read
         compute_slot(slot);
         slot = slot + 1 == S ? 0 : slot + 1;
     }
@@ -844,23 +938,26 @@ bool mfma_supported(uint32_t variant, const Geometry& g, uint32_t qt, uint32_t u
     if (g.R % 32 != 0) return false;  // whole 256-column tiles
     // unroll selects the pipeline: 1 = one K-step ahead in registers;
     // 3, 4, 6 = an LDS ring of that many stages (that many minus one K-steps
-    // in flight), within the 160 KiB of LDS a workgroup may use
+    // in flight), within the 160 KiB of LDS a workgroup may use; 7 = a
+    // 3-stage ring whose selection operand is spread once per workgroup
+    // (fp4, 64-query tiles)
+    if (unroll == 7) return variant == PIR_VARIANT_MFMA_F4 && qt == 64;
     if (unroll != 1 && unroll != 3 && unroll != 4 && unroll != 6) return false;
     return qt == 16 || qt == 32 || qt == 64;
 }
 
-template <int MT, bool F4, int S>
+template <int MT, bool F4, int S, bool SA = false>
 static hipError_t launch_ring(dim3 grid, hipStream_t s, const uint32_t* db, const uint32_t* sel, uint8_t* partials,
                               const Stage1Params& p) {
-    constexpr uint32_t bytes = ring_bytes<MT>(S);
+    constexpr uint32_t bytes = ring_bytes<MT>(S) + (SA ? 16u * 1024u : 0u);
     static bool attr_set = false;  // the dynamic-LDS limit is raised once per instance
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage1_mfma_lds<MT, F4, S>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage1_mfma_lds<MT, F4, S, SA>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_stage1_mfma_lds<MT, F4, S>), grid, dim3(kThreads), bytes, s, db, sel, partials, p);
+    hipLaunchKernelGGL((k_stage1_mfma_lds<MT, F4, S, SA>), grid, dim3(kThreads), bytes, s, db, sel, partials, p);
     return hipGetLastError();
 }
 
@@ -889,6 +986,9 @@ static hipError_t launch_mfma_t(const Geometry& g, const Plan& pl, const void* d
         case 3: return launch_ring<MT, F4, 3>(grid, s, d, sel, partials, p);
         case 4: return launch_ring<MT, F4, 4>(grid, s, d, sel, partials, p);
         case 6: return launch_ring<MT, F4, 6>(grid, s, d, sel, partials, p);
+        case 7:
+            if constexpr (MT == 4 && F4) return launch_ring<4, true, 3, true>(grid, s, d, sel, partials, p);
+            return hipErrorInvalidValue;
         default:
             hipLaunchKernelGGL((k_stage1_mfma<MT, F4>), grid, dim3(kThreads), 0, s, d, sel, partials, p);
             return hipGetLastError();

@@ -70,7 +70,8 @@ def test_c4_variants_agree(c4, q):
     for i, want in rows.items():
         if i < q:
             assert np.array_equal(ref[i], want)
-    for cfg in (pir.KernelCfg(pir.PIR_VARIANT_MFMA_I8, 64, 6, 0),
+    for cfg in (pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 7, 0),
+                pir.KernelCfg(pir.PIR_VARIANT_MFMA_I8, 64, 6, 0),
                 pir.KernelCfg(pir.PIR_VARIANT_MFMA_I8, 32, 1, 0),
                 pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 32, 3, 0),
                 pir.KernelCfg(pir.PIR_VARIANT_VALU, 16, 4, 0)):
