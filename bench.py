@@ -54,7 +54,7 @@ def kernel_name(cfg, r):
         return f"k_stage1_valu<{cfg.q_tile}, {cfg.unroll}, {'true' if r < 32 else 'false'}>"
     mt = cfg.q_tile // 16
     f4 = "true" if cfg.variant == 3 else "false"
-    if cfg.unroll in (3, 4, 6):  # LDS ring of that many stages
+    if cfg.unroll in (2, 3, 4, 6):  # LDS ring of that many stages
         return f"k_stage1_mfma_lds<{mt}, {f4}, {cfg.unroll}, false>"
     if cfg.unroll == 7:  # 3-stage ring, selection operand spread once per workgroup
         return f"k_stage1_mfma_lds<{mt}, {f4}, 3, true>"

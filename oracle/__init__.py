@@ -1,4 +1,4 @@
-"""ORACLE for dpXOR -- test infrastructure only.
+"""ORACLE for dpXOR and the DPF step before it -- test infrastructure only.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  The product path never does, and shares
@@ -11,6 +11,12 @@ subresult (IM-PIR Sec. 2 "Multi-Server PIR", the equation for r; Sec. 3.3
 (Fig. 2 and its DPF restatement, fixture tests/golden/), brute force over all
 selections of tiny databases against an integer-count formulation, the
 two-server reconstruction identity, special cases and linearity.
+
+``dpf_oracle.c`` is AES-128 (FIPS-197) and the DPF of IM-PIR Sec. 3.1-3.2
+(eq. 1-3; key generation after Boyle-Gilboa-Ishai 2016).  Its pins
+(tests/test_dpf_oracle.py): FIPS-197 and SP 800-38A known answers, the
+S-box values FIPS-197 prints, and the point-function identity
+Eval(k0, x) XOR Eval(k1, x) = [x = alpha] by brute force.
 """
 import ctypes
 import os
@@ -19,7 +25,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "dpxor_oracle.c")
+_SRCS = [os.path.join(_HERE, "dpxor_oracle.c"), os.path.join(_HERE, "dpf_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared"]
 _lib = None
@@ -28,17 +34,34 @@ _lib = None
 def build():
     """Compile liboracle.so with gcc (always recompiles)."""
     tmp = _LIB + ".tmp"
-    subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC])
+    subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, *_SRCS])
     os.replace(tmp, _LIB)
 
 
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        stale = not os.path.exists(_LIB) or any(
+            os.path.getmtime(_LIB) < os.path.getmtime(src) for src in _SRCS)
+        if stale:
             build()
         lib = ctypes.CDLL(_LIB)
         p, u64, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
+        i32 = ctypes.c_int
+        lib.oracle_aes_sbox.restype = ctypes.c_uint8
+        lib.oracle_aes_sbox.argtypes = [ctypes.c_uint8]
+        lib.oracle_aes128_encrypt.restype = None
+        lib.oracle_aes128_encrypt.argtypes = [p, p, p]
+        lib.oracle_dpf_key_bytes.restype = u64
+        lib.oracle_dpf_key_bytes.argtypes = [i32]
+        lib.oracle_dpf_eval_block.restype = None
+        lib.oracle_dpf_eval_block.argtypes = [p, i32, u64, p]
+        lib.oracle_dpf_eval_bit.restype = i32
+        lib.oracle_dpf_eval_bit.argtypes = [p, i32, u64]
+        lib.oracle_dpf_eval_full.restype = None
+        lib.oracle_dpf_eval_full.argtypes = [p, i32, p]
+        lib.oracle_dpf_gen.restype = None
+        lib.oracle_dpf_gen.argtypes = [u64, i32, p, p, p, p]
         lib.oracle_dpxor.restype = None
         lib.oracle_dpxor.argtypes = [p, u64, u32, p, p]
         lib.oracle_dpxor_batch.restype = None
@@ -87,4 +110,52 @@ def reconstruct(r1, r2):
     assert r1.shape == r2.shape
     out = np.empty_like(r1)
     _load().oracle_reconstruct(r1.ctypes.data, r2.ctypes.data, r1.size, out.ctypes.data)
+    return out
+
+
+# ---------------------------------------------------------------- AES / DPF
+
+def aes_sbox(x):
+    return int(_load().oracle_aes_sbox(x))
+
+
+def aes128_encrypt(key, block):
+    key = _u8(key).reshape(-1)
+    block = _u8(block).reshape(-1)
+    assert key.size == 16 and block.size == 16
+    out = np.empty(16, np.uint8)
+    _load().oracle_aes128_encrypt(key.ctypes.data, block.ctypes.data, out.ctypes.data)
+    return out
+
+
+def dpf_key_bytes(n):
+    return int(_load().oracle_dpf_key_bytes(n))
+
+
+def dpf_gen(alpha, n, root0, root1):
+    """Keys (k0, k1) of P_{alpha,1} over 2^n points; roots are 16 random bytes each."""
+    kb = dpf_key_bytes(n)
+    k0, k1 = np.zeros(kb, np.uint8), np.zeros(kb, np.uint8)
+    r0, r1 = _u8(root0).reshape(-1), _u8(root1).reshape(-1)
+    _load().oracle_dpf_gen(alpha, n, r0.ctypes.data, r1.ctypes.data, k0.ctypes.data, k1.ctypes.data)
+    return k0, k1
+
+
+def dpf_eval_block(key, n, j):
+    out = np.empty(16, np.uint8)
+    key = _u8(key)
+    _load().oracle_dpf_eval_block(key.ctypes.data, n, j, out.ctypes.data)
+    return out
+
+
+def dpf_eval_bit(key, n, j):
+    key = _u8(key)
+    return int(_load().oracle_dpf_eval_bit(key.ctypes.data, n, j))
+
+
+def dpf_eval_full(key, n):
+    """Packed selection vector of 2^n bits (LSB first)."""
+    key = _u8(key)
+    out = np.zeros(((1 << n) + 7) // 8, np.uint8)
+    _load().oracle_dpf_eval_full(key.ctypes.data, n, out.ctypes.data)
     return out

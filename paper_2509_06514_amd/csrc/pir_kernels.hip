@@ -573,7 +573,7 @@ k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
     constexpr int QT = 16 * MT;
     constexpr int kLoadsPerStep = 4 + MT;  // per wave: 4 database chunks + MT selection rows-of-4
     constexpr uint32_t kStageSelBytes = QT * 16 * 4;
-    static_assert(S >= 3 && S <= 8, "ring stages");
+    static_assert(S >= 2 && S <= 8, "ring stages");
     static_assert(!SA || (MT == 4 && F4), "shared spread: fp4, four row tiles");
     extern __shared__ __attribute__((aligned(16))) uint8_t pir_ring[];
     uint8_t* const ring_db = pir_ring;                        // S x [16 blocks][256 words]
@@ -610,7 +610,8 @@ k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
         for (int i = 0; i < 4; ++i) {
             const uint32_t b = 4 * i + wave;
             const uint32_t* base = db_tile + (kb + b) * block_words;  // uniform
-            __builtin_amdgcn_global_load_lds(base + 4 * lane, dst_db + b * 1024, 16, 0, 0);
+            // database chunks are read once: nontemporal (cache policy NT = 2)
+            __builtin_amdgcn_global_load_lds(base + 4 * lane, dst_db + b * 1024, 16, 0, 2);
         }
 #pragma unroll
         for (int i = 0; i < MT; ++i)
@@ -937,12 +938,12 @@ bool mfma_supported(uint32_t variant, const Geometry& g, uint32_t qt, uint32_t u
     if (variant != PIR_VARIANT_MFMA_F4 && variant != PIR_VARIANT_MFMA_I8) return false;
     if (g.R % 32 != 0) return false;  // whole 256-column tiles
     // unroll selects the pipeline: 1 = one K-step ahead in registers;
-    // 3, 4, 6 = an LDS ring of that many stages (that many minus one K-steps
+    // 2, 3, 4, 6 = an LDS ring of that many stages (that many minus one K-steps
     // in flight), within the 160 KiB of LDS a workgroup may use; 7 = a
     // 3-stage ring whose selection operand is spread once per workgroup
     // (fp4, 64-query tiles)
     if (unroll == 7) return variant == PIR_VARIANT_MFMA_F4 && qt == 64;
-    if (unroll != 1 && unroll != 3 && unroll != 4 && unroll != 6) return false;
+    if (unroll != 1 && unroll != 2 && unroll != 3 && unroll != 4 && unroll != 6) return false;
     return qt == 16 || qt == 32 || qt == 64;
 }
 
@@ -983,6 +984,7 @@ static hipError_t launch_mfma_t(const Geometry& g, const Plan& pl, const void* d
     const dim3 grid((total + 7) / 8 * 8);
     const uint32_t* d = (const uint32_t*)db;
     switch (pl.unroll) {
+        case 2: return launch_ring<MT, F4, 2>(grid, s, d, sel, partials, p);
         case 3: return launch_ring<MT, F4, 3>(grid, s, d, sel, partials, p);
         case 4: return launch_ring<MT, F4, 4>(grid, s, d, sel, partials, p);
         case 6: return launch_ring<MT, F4, 6>(grid, s, d, sel, partials, p);

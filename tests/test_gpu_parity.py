@@ -205,7 +205,7 @@ def test_mfma_variants(ctx, variant, n, r):
     for q in qs:
         d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
         for qt in (16, 32, 64):
-            for unroll in (1, 3, 4, 6, 7):  # registers, LDS rings of 3/4/6 stages, shared spread
+            for unroll in (1, 2, 3, 4, 6, 7):  # registers, LDS rings of 2/3/4/6 stages, shared spread
                 if unroll == 7 and not (variant == pir.PIR_VARIANT_MFMA_F4 and qt == 64):
                     continue
                 for groups in (0, 3, 1):
