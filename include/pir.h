@@ -186,6 +186,8 @@ typedef struct pir_timing {
     double stage1_ms;
     uint64_t stage2_launches;
     double stage2_ms;
+    uint64_t dpf_evals;       /* DPF evaluations (each a chain of expansion kernels) */
+    double dpf_ms;            /* their summed durations, first launch to last */
 } pir_timing;
 
 int pir_timing_enable(pir_ctx* ctx, int on);
@@ -256,6 +258,69 @@ int pir_serve_stats_get(pir_server* srv, pir_serve_stats* out, int reset);
  * scheduler and free the slots.  Every ticket completes or reports
  * PIR_E_SHUTDOWN; none is lost. */
 int pir_serve_destroy(pir_server* srv);
+
+/* ---------------------------------------------------------------- DPF */
+
+/*
+ * Distributed point functions (IM-PIR Sec. 3.1 key generation, Sec. 3.2
+ * evaluation, eq. 1-3) over a domain of 2^n leaves:
+ *
+ *   Eval(k, j) = R(n, j),   R(0, 0) = C0[0, 0],
+ *   R(d, j) = PRF_{R(d-1, j/2)}(j mod 2) XOR C_{R(d-1, j/2) mod 2}[j mod 2, d].
+ *
+ * Node values are 16-byte blocks; "mod 2" is bit 0 of byte 0; PRF_s(x) is
+ * AES-128 (FIPS-197) under key s of the block whose byte 0 is x and whose
+ * other bytes are 0.  The selection bit of leaf j is bit 0 of byte 0 of
+ * Eval(k, j); the two parties' bits differ exactly at alpha.
+ *
+ * Key layout (pir_dpf_key_bytes(n) = 64 * (n + 1) bytes): codeword C0 then
+ * codeword C1, each 2 x (n+1) blocks; block [x][d] of codeword c at byte
+ * ((2c + x) * (n + 1) + d) * 16.
+ */
+uint64_t pir_dpf_key_bytes(uint32_t n);
+
+/* Smallest n with 2^n >= n_records (0 for n_records <= 1): the domain a
+ * database's keys are generated for. */
+uint32_t pir_dpf_domain_bits(uint64_t n_records);
+
+/*
+ * Client side, host only (no device is touched).  Writes the two parties'
+ * keys for the point function that is 1 at alpha (alpha < 2^n, n <= 62):
+ * the tree construction of Boyle, Gilboa and Ishai (CCS 2016) that the paper
+ * refers to, in the codeword form above -- C0[0][0] is the party's root, all
+ * other C0 blocks are zero, C1 holds the per-level correction words (equal in
+ * both keys).  root0/root1: 16 bytes each that the caller draws from a
+ * cryptographic random source; their bit 0 is replaced by the party index.
+ * key0/key1: pir_dpf_key_bytes(n) bytes each, caller-owned.
+ */
+int pir_dpf_gen(uint64_t alpha, uint32_t n, const uint8_t* root0, const uint8_t* root1, uint8_t* key0,
+                uint8_t* key1);
+
+/*
+ * Full-domain evaluation on the device, asynchronous on hip_stream.
+ * d_keys: n_keys keys of pir_dpf_key_bytes(n) bytes, consecutive, 16-byte
+ * aligned, device memory.  Row q of d_sel (rows sel_stride bytes apart,
+ * sel_stride a multiple of 4 and >= 4 * ceil(n_leaves / 32), base 4-byte
+ * aligned) receives words [0, ceil(n_leaves / 32)): bit j = Eval(k_q, j),
+ * LSB first, for every j < min(2^n, 32 * ceil(n_leaves / 32)); the words
+ * past that are not written.  1 <= n_leaves <= 2^n, n <= 40,
+ * 1 <= n_keys <= PIR_MAX_BATCH.  The library keeps a scratch buffer per
+ * stream for the tree levels (2 * ceil(n_leaves / 32) blocks per key in flight,
+ * keys processed in groups of at most 1 GiB of scratch) and may synchronise
+ * the stream once to grow it.  Errors: PIR_E_INVAL, PIR_E_NOMEM, PIR_E_DEVICE.
+ */
+int pir_dpf_eval_async(pir_ctx* ctx, const void* d_keys, uint32_t n, uint32_t n_keys, uint64_t n_leaves,
+                       void* d_sel, uint64_t sel_stride, void* hip_stream);
+
+/*
+ * A server's whole answer from keys (Sec. 3.2 then Sec. 3.3): evaluates
+ * n_keys keys for the database's domain (n = pir_dpf_domain_bits(N)) into a
+ * library-owned selection workspace and scans the database with them in
+ * batches; row q of d_out (n_keys * R bytes, device) = XOR over j < N of
+ * Eval(k_q, j) * D[j].  Same key layout and alignment as pir_dpf_eval_async;
+ * asynchronous on hip_stream, with the same workspace rules.
+ */
+int pir_dpf_dpxor_async(pir_db* db, const void* d_keys, uint32_t n_keys, void* d_out, void* hip_stream);
 
 /* ---------------------------------------------------------------- memory */
 

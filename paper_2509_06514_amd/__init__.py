@@ -13,6 +13,7 @@ from ._native import (PIR_MAX_BATCH, PIR_VARIANT_AUTO, PIR_VARIANT_MFMA_F4, PIR_
                       PIR_VARIANT_VALU, PirError, check, lib)
 
 __all__ = ["Context", "Database", "Server", "KernelCfg", "PirError", "lib", "sel_stride_for",
+           "dpf_key_bytes", "dpf_domain_bits", "dpf_gen",
            "PIR_MAX_BATCH", "PIR_VARIANT_AUTO", "PIR_VARIANT_VALU", "PIR_VARIANT_MFMA_I8",
            "PIR_VARIANT_MFMA_F4"]
 
@@ -64,6 +65,30 @@ def sel_stride_for(n_records, align=256):
     return (4 * words + align - 1) // align * align
 
 
+def dpf_key_bytes(n):
+    """Bytes of one DPF key over a 2^n domain: codewords C0, C1 of 2 x (n+1) 16-byte blocks."""
+    return int(lib().pir_dpf_key_bytes(n))
+
+
+def dpf_domain_bits(n_records):
+    """Smallest n with 2^n >= n_records."""
+    return int(lib().pir_dpf_domain_bits(n_records))
+
+
+def dpf_gen(alpha, n, root0, root1):
+    """Client-side key generation (host): the two parties' keys for the point at alpha.
+
+    root0/root1: 16 random bytes each (bit 0 is replaced by the party index).
+    """
+    r0, r1 = _u8(root0).reshape(-1), _u8(root1).reshape(-1)
+    if r0.size != 16 or r1.size != 16:
+        raise ValueError("roots must be 16 bytes")
+    kb = dpf_key_bytes(n)
+    k0, k1 = np.empty(kb, np.uint8), np.empty(kb, np.uint8)
+    check(lib().pir_dpf_gen(alpha, n, _ptr(r0), _ptr(r1), _ptr(k0), _ptr(k1)), "pir_dpf_gen")
+    return k0, k1
+
+
 class Context:
     """A device context (pir_ctx)."""
 
@@ -96,7 +121,27 @@ class Context:
         t = _native.pir_timing()
         check(lib().pir_timing_read(self._h, ctypes.byref(t), 1 if reset else 0), "pir_timing_read")
         return {"stage1_launches": t.stage1_launches, "stage1_ms": t.stage1_ms,
-                "stage2_launches": t.stage2_launches, "stage2_ms": t.stage2_ms}
+                "stage2_launches": t.stage2_launches, "stage2_ms": t.stage2_ms,
+                "dpf_evals": t.dpf_evals, "dpf_ms": t.dpf_ms}
+
+    def dpf_eval_async(self, d_keys, n, n_keys, n_leaves, d_sel, sel_stride=None, stream=None):
+        """Full-domain DPF evaluation on the device (torch tensors), enqueued on `stream`.
+
+        d_keys: n_keys consecutive keys of dpf_key_bytes(n) bytes; row q of d_sel
+        (sel_stride bytes apart) receives the packed selection bits of key q.
+        """
+        if d_keys.device.type != "cuda" or d_sel.device.type != "cuda":
+            raise ValueError("device tensors required")
+        if d_keys.numel() * d_keys.element_size() < n_keys * dpf_key_bytes(n):
+            raise ValueError("d_keys too small")
+        words = (n_leaves + 31) // 32
+        if sel_stride is None:
+            sel_stride = d_sel.stride(0) * d_sel.element_size() if d_sel.dim() == 2 else 4 * words
+        if d_sel.numel() * d_sel.element_size() < (n_keys - 1) * sel_stride + 4 * words:
+            raise ValueError("d_sel too small")
+        check(lib().pir_dpf_eval_async(self._h, ctypes.c_void_p(d_keys.data_ptr()), n, n_keys, n_leaves,
+                                       ctypes.c_void_p(d_sel.data_ptr()), sel_stride, _stream_handle(stream)),
+              "pir_dpf_eval_async")
 
     def close(self):
         if self._h:
@@ -172,6 +217,19 @@ class Database:
             rc = lib().pir_dpxor_batch_async_cfg(self._h, ctypes.c_void_p(d_sel.data_ptr()), sel_stride, q,
                                                  ctypes.c_void_p(d_out.data_ptr()), s, ctypes.byref(c))
         check(rc, "pir_dpxor_batch_async")
+
+    def dpf_dpxor_async(self, d_keys, n_keys, d_out, stream=None):
+        """Answers from DPF keys: row q of d_out = XOR_j Eval(k_q, j) * D[j] (device tensors)."""
+        n = dpf_domain_bits(self.n_records)
+        if d_keys.device.type != "cuda" or d_out.device.type != "cuda":
+            raise ValueError("device tensors required")
+        if d_keys.numel() * d_keys.element_size() < n_keys * dpf_key_bytes(n):
+            raise ValueError("d_keys too small")
+        if d_out.numel() * d_out.element_size() < n_keys * self.record_bytes:
+            raise ValueError("d_out too small")
+        check(lib().pir_dpf_dpxor_async(self._h, ctypes.c_void_p(d_keys.data_ptr()), n_keys,
+                                        ctypes.c_void_p(d_out.data_ptr()), _stream_handle(stream)),
+              "pir_dpf_dpxor_async")
 
     def get_cfg(self, q):
         c = _native.pir_kernel_cfg()

@@ -44,7 +44,8 @@ class pir_kernel_cfg(ctypes.Structure):
 
 class pir_timing(ctypes.Structure):
     _fields_ = [("stage1_launches", ctypes.c_uint64), ("stage1_ms", ctypes.c_double),
-                ("stage2_launches", ctypes.c_uint64), ("stage2_ms", ctypes.c_double)]
+                ("stage2_launches", ctypes.c_uint64), ("stage2_ms", ctypes.c_double),
+                ("dpf_evals", ctypes.c_uint64), ("dpf_ms", ctypes.c_double)]
 
 
 class pir_serve_config(ctypes.Structure):
@@ -96,6 +97,11 @@ SIGNATURES = {
     "pir_serve_poll": (_I, [_P, _U64, ctypes.POINTER(_I)]),
     "pir_serve_stats_get": (_I, [_P, ctypes.POINTER(pir_serve_stats), _I]),
     "pir_serve_destroy": (_I, [_P]),
+    "pir_dpf_key_bytes": (_U64, [_U32]),
+    "pir_dpf_domain_bits": (_U32, [_U64]),
+    "pir_dpf_gen": (_I, [_U64, _U32, _P, _P, _P, _P]),
+    "pir_dpf_eval_async": (_I, [_P, _P, _U32, _U32, _U64, _P, _U64, _P]),
+    "pir_dpf_dpxor_async": (_I, [_P, _P, _U32, _P, _P]),
     "pir_host_alloc": (_P, [ctypes.c_size_t]),
     "pir_host_free": (None, [_P]),
 }

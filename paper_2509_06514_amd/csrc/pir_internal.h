@@ -73,4 +73,21 @@ hipError_t launch_slice(const Geometry& g, const uint8_t* src, uint64_t nrec, ui
 hipError_t launch_unslice(const Geometry& g, const uint32_t* src_block0, uint64_t nblk, uint8_t* dst,
                           uint64_t nrec, hipStream_t s);
 
+// DPF (pir_dpf.hip).
+constexpr uint32_t kDpfBlock = 256;  // threads per workgroup of the expansion kernels
+uint64_t dpf_key_bytes(uint32_t n);
+// nodes per key in each of the two scratch buffers of an evaluation
+uint64_t dpf_scratch_nodes(uint32_t n, uint64_t n_leaves);
+// launch chain as (first level, levels expanded); returns the number of launches
+int dpf_plan(uint32_t n, uint64_t n_leaves, uint32_t n_keys, uint32_t steps[][2]);
+// full-domain evaluation of n_keys keys (device, dpf_key_bytes(n) apart):
+// selection words [0, ceil(n_leaves / 32)) of row q at d_sel + q * stride_words;
+// scratch holds 2 * n_keys * scratch_nodes 16-byte nodes
+hipError_t launch_dpf_eval(int device, const uint8_t* d_keys, uint32_t n, uint32_t n_keys, uint64_t n_leaves,
+                           uint32_t* d_sel, uint64_t stride_words, void* scratch, uint64_t scratch_nodes,
+                           hipStream_t s);
+void dpf_gen_host(uint64_t alpha, uint32_t n, const uint8_t root0[16], const uint8_t root1[16], uint8_t* key0,
+                  uint8_t* key1);
+void aes128_encrypt_host(const uint8_t key[16], const uint8_t in[16], uint8_t out[16]);
+
 }  // namespace pir

@@ -153,6 +153,10 @@ Ctx::~Ctx() {
     }
     pool.clear();
     for (auto& kv : workspaces) kv.second.reset();
+    for (auto& kv : dpf_ws) {
+        kv.second.nodes.reset();
+        kv.second.sel.reset();
+    }
     std::vector<hipEvent_t> evs(free_events);
     for (auto& t : pending) {
         evs.push_back(t.a);
@@ -200,6 +204,11 @@ hipEvent_t Ctx::take_event() {
     hipEvent_t ev = nullptr;
     if (hipEventCreate(&ev) != hipSuccess) return nullptr;
     return ev;
+}
+
+void Ctx::add_timed(hipEvent_t a, hipEvent_t b, int stage) {
+    std::lock_guard<std::mutex> lk(mu);
+    pending.push_back({a, b, stage});
 }
 
 // Enqueue stage 1 + stage 2 for q queries on `s` with scratch `partials`.
@@ -753,9 +762,12 @@ int pir_timing_read(pir_ctx* c, pir_timing* out, int reset) {
         if (t.stage == 1) {
             ctx->acc.stage1_launches++;
             ctx->acc.stage1_ms += ms;
-        } else {
+        } else if (t.stage == 2) {
             ctx->acc.stage2_launches++;
             ctx->acc.stage2_ms += ms;
+        } else {
+            ctx->acc.dpf_evals++;
+            ctx->acc.dpf_ms += ms;
         }
     }
     // e1 appears in two records (end of stage 1, start of stage 2): free each event once

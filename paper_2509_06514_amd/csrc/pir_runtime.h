@@ -67,6 +67,12 @@ struct Db {
     std::mutex mu;                  // serialises updates and reads
 };
 
+// Per-stream scratch of the DPF calls: tree levels, and the selection rows
+// the key-to-answer path hands from the evaluation to the scan.
+struct DpfWs {
+    DevBuf nodes, sel;
+};
+
 struct Ctx {
     int device = 0;
     std::string arch;
@@ -74,6 +80,7 @@ struct Ctx {
     std::mutex mu;
     std::vector<std::unique_ptr<Exec>> pool;
     std::unordered_map<hipStream_t, DevBuf> workspaces;  // per caller stream
+    std::unordered_map<hipStream_t, DpfWs> dpf_ws;       // per caller stream
     std::map<std::string, pir_kernel_cfg> tuned;
     std::atomic<bool> timing_on{false};
     std::vector<TimedPair> pending;
@@ -86,6 +93,8 @@ struct Ctx {
     void release(Exec* e);
     hipEvent_t take_event();
     int plan_for(const Db& db, uint32_t q, const pir_kernel_cfg* cfg, Plan& p);
+    // records (a, b) as a timed interval of `stage` (1, 2: scan stages; 3: DPF evaluation)
+    void add_timed(hipEvent_t a, hipEvent_t b, int stage);
     int enqueue_scan(const Db& db, const Plan& p, const uint32_t* d_sel, uint64_t stride_words, uint32_t q,
                      uint8_t* d_out, uint8_t* partials, hipStream_t s);
     std::string tune_key(const Geometry& g, uint32_t q) const;

@@ -19,10 +19,12 @@ _lib = None
 MASK64 = (1 << 64) - 1
 GAMMA = 0x9E3779B97F4A7C15
 
-# Seeds per workload: database stream, selection streams, point-index stream.
+# Seeds per workload: database stream, selection streams, point-index stream,
+# DPF key material (root seeds, random codewords).
 S_DB = 0x1000
 S_SEL = 0x2000
 S_IDX = 0x3000
+S_KEY = 0x4000
 
 
 def build():

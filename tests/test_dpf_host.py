@@ -1,0 +1,54 @@
+"""Host-side DPF logic of the library (no device work): client key generation
+(IM-PIR Sec. 3.1) must produce byte-identical keys to the oracle's, plus the
+key-size and domain helpers and argument checks."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_2509_06514_amd as pir
+from paper_2509_06514_amd import _native
+
+
+def _roots(seed):
+    b = synth.stream_bytes(seed, 32)
+    return b[:16], b[16:]
+
+
+def test_key_bytes_and_domain_bits():
+    for n in (0, 1, 5, 28, 40):
+        assert pir.dpf_key_bytes(n) == oracle.dpf_key_bytes(n) == 64 * (n + 1)
+    assert [pir.dpf_domain_bits(x) for x in (0, 1, 2, 3, 4, 5, 1 << 28, (1 << 28) + 1)] == \
+        [0, 0, 1, 2, 2, 3, 28, 29]
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 7, 13, 28, 40])
+def test_gen_matches_oracle(n):
+    rng = np.random.default_rng(n)
+    for t in range(4):
+        alpha = int(rng.integers(0, 1 << n)) if n else 0
+        r0, r1 = _roots(synth.S_KEY + 17 * n + t)
+        k0, k1 = pir.dpf_gen(alpha, n, r0, r1)
+        o0, o1 = oracle.dpf_gen(alpha, n, r0, r1)
+        assert np.array_equal(k0, o0) and np.array_equal(k1, o1), (n, alpha)
+
+
+def test_gen_keys_share_correction_words():
+    n = 10
+    r0, r1 = _roots(synth.S_KEY + 3)
+    k0, k1 = pir.dpf_gen(777, n, r0, r1)
+    half = pir.dpf_key_bytes(n) // 2
+    assert np.array_equal(k0[half:], k1[half:])      # C1 identical
+    assert k0[0] & 1 == 0 and k1[0] & 1 == 1          # party bits of the roots
+    assert not k0[16:half].any() and not k1[16:half].any()  # C0 beyond the root is zero
+
+
+def test_gen_rejects_bad_arguments():
+    lib = pir.lib()
+    buf = np.zeros(64 * 64, np.uint8)
+    p = buf.ctypes.data
+    assert lib.pir_dpf_gen(4, 2, p, p, p, p) == _native.PIR_E_INVAL   # alpha >= 2^n
+    assert lib.pir_dpf_gen(0, 63, p, p, p, p) == _native.PIR_E_INVAL  # n too large
+    assert lib.pir_dpf_gen(0, 2, None, p, p, p) == _native.PIR_E_INVAL
+    assert lib.pir_dpf_eval_async(None, None, 1, 1, 1, None, 4, None) == _native.PIR_E_INVAL
+    assert lib.pir_dpf_dpxor_async(None, None, 1, None, None) == _native.PIR_E_INVAL
