@@ -142,6 +142,106 @@ def cpu_baseline(db_host, sel_rows, n, r, sample_queries):
             "db_gbs_scanned": sample_queries * n * r / dt / 1e9}
 
 
+# VALU operations per tree-node expansion of the DPF evaluation (AES-128 in
+# the one-T-table form: one v_perm per lookup address, three rotations and
+# two three-input XORs per MixColumns column, 11 ops per key-schedule round):
+#   full (both 128-bit children): 110 key schedule + 1 + 45 round 1 (the second
+#     block differs only in column 0) + 576 rounds 2-9 + 56 last round + 18
+#     correction words = 806
+#   leaf (bit 0 of both children, at the last level): 99 + 3 key schedule + 1 +
+#     45 + 504 rounds 2-8 + 18 round 9 (column 0) + 6 last round (byte 0) + 10 = 686
+DPF_OPS_FULL = 806
+DPF_OPS_LEAF = 686
+
+
+def dpf_bench(ctx, db, db_host, n, r, args, torch, pir):
+    """DPF evaluation on the database's domain and answers straight from keys."""
+    import numpy as np
+    import synth
+
+    nb = pir.dpf_domain_bits(n)
+    nk = args.dpf_keys
+    rng = np.random.default_rng(11)
+    alphas = [int(a) for a in rng.integers(0, n, nk // 2)]
+    keys = []
+    for i, a in enumerate(alphas):
+        root = synth.stream_bytes(synth.S_KEY + 900 + i, 32)
+        k0, k1 = pir.dpf_gen(a, nb, root[:16], root[16:])
+        keys += [k0, k1]
+    d_keys = torch.from_numpy(np.stack(keys)).to("cuda:0")
+    words = (n + 31) // 32
+    d_sel = torch.empty((nk, words), dtype=torch.int32, device="cuda:0")
+
+    def step_eval():
+        ctx.dpf_eval_async(d_keys, nb, nk, n, d_sel)
+
+    for _ in range(2):
+        step_eval()
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.timing_read(reset=True)
+    wall, _ = time_steps(step_eval, args.dpf_steps, torch)
+    t = ctx.timing_read(reset=True)
+    ctx.timing(False)
+    ms = t["dpf_ms"] / max(1, t["dpf_evals"])
+    # Eval(k0) XOR Eval(k1) is the indicator of alpha
+    ok = True
+    for i, a in enumerate(alphas):
+        x = d_sel[2 * i] ^ d_sel[2 * i + 1]
+        nz = torch.nonzero(x).flatten().cpu().tolist()
+        ok &= nz == [a // 32] and (int(x[a // 32].item()) & 0xFFFFFFFF) == 1 << (a % 32)
+    half = 1 << (nb - 1) if nb else 0
+    ops = ((half - 1) * DPF_OPS_FULL + half * DPF_OPS_LEAF) * nk if n == 1 << nb else None
+    out = {
+        "domain_bits": nb, "keys_per_call": nk, "ms_per_call": ms, "ms_per_key": ms / nk,
+        "leaves_per_s": nk * n / (ms / 1e3), "node_expansions_per_s": nk * ((1 << nb) - 1) / (ms / 1e3),
+        "point_function_check": bool(ok),
+    }
+    if ops is not None:
+        ach = ops / (ms / 1e3) / 1e12
+        out["roofline"] = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                           "frac": ach / VALU_PEAK_TOPS, "traffic": None,
+                           "algorithmic_ops_per_launch": ops, "avg_launch_ms": ms,
+                           "ops_per_expansion": {"full": DPF_OPS_FULL, "leaf": DPF_OPS_LEAF}}
+    log(f"DPF eval: {ms / nk:.3f} ms per key (2^{nb} leaves), point check {ok}")
+
+    # answers from keys: evaluation into a workspace, then the batched scan
+    d_ans = torch.empty((nk, r), dtype=torch.uint8, device="cuda:0")
+
+    def step_answer():
+        db.dpf_dpxor_async(d_keys, nk, d_ans)
+
+    step_answer()
+    torch.cuda.synchronize()
+    wall_a, _ = time_steps(step_answer, args.dpf_steps, torch)
+    ans = d_ans.cpu().numpy()
+    ok_a = all(np.array_equal(ans[2 * i] ^ ans[2 * i + 1], db_host[a]) for i, a in enumerate(alphas))
+    out["key_to_answer"] = {"queries_per_s": nk * args.dpf_steps / wall_a,
+                            "ms_per_call": wall_a / args.dpf_steps * 1e3, "two_server_check": bool(ok_a)}
+    log(f"keys -> answers: {out['key_to_answer']['queries_per_s']:.1f} q/s, two-server check {ok_a}")
+    if args.cpu_sample > 0:
+        out["cpu_baseline"] = dpf_cpu_baseline(keys[0])
+    return out
+
+
+def dpf_cpu_baseline(key_full_domain):
+    """The oracle's DPF evaluation, one host thread, on a 2^16-leaf domain."""
+    import numpy as np
+    import oracle
+    import paper_2509_06514_amd as pir
+    import synth
+
+    nb = 16
+    root = synth.stream_bytes(synth.S_KEY + 999, 32)
+    k0, _ = pir.dpf_gen(12345, nb, root[:16], root[16:])
+    t0 = time.perf_counter()
+    oracle.dpf_eval_full(k0, nb)
+    dt = time.perf_counter() - t0
+    return {"value": (1 << nb) / dt, "unit": "leaves/s", "cores": 1, "kind": "oracle",
+            "sample": f"one key over 2^{nb} leaves (each leaf evaluated root to leaf, as eq. 1-3 "
+                      f"read), {dt:.2f} s on 1 host thread"}
+
+
 SERVE_DBS = [(1 << 23, 32), (1 << 24, 128), (1 << 22, 1024)]
 
 
@@ -241,6 +341,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="use the default kernel plan")
     ap.add_argument("--cpu-sample", type=int, default=2, help="oracle queries for cpu_baseline (0 = skip)")
     ap.add_argument("--no-single", action="store_true", help="skip the single-query pass")
+    ap.add_argument("--dpf-keys", type=int, default=8,
+                    help="DPF keys (pairs of parties) evaluated per call in the DPF section (0 = skip)")
+    ap.add_argument("--dpf-steps", type=int, default=5)
     ap.add_argument("--serve", action="store_true", help="run the serving sweep (three resident DBs) instead")
     ap.add_argument("--serve-rates", default="1000,2000,5000,10000,20000,50000")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
@@ -382,6 +485,9 @@ def main():
     # is covered by the tests; here only that the answers are not all zero
     ans = d_out.cpu().numpy()
     result["answers_nonzero"] = bool(ans.any())
+
+    if args.dpf_keys > 0:
+        result["dpf"] = dpf_bench(ctx, db, db_host, n, r, args, torch, pir)
 
     if args.cpu_sample > 0:
         log(f"cpu_baseline: oracle on {args.cpu_sample} queries ...")

@@ -25,7 +25,9 @@
 // the S-box itself is its byte 1).  The table is replicated once per lane of
 // a wave in LDS -- entry i of lane l at byte 256*i + 4*l -- so the lookups of
 // a wave never collide in a bank and each address is a single v_perm_b32 of
-// the state word and the lane offset.
+// the state word and the lane offset.  (A second, pre-rotated table would
+// save two rotations per column, but at 128 KiB of LDS per workgroup it
+// halves the waves per CU and measured slower.)
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -202,6 +204,12 @@ __device__ __forceinline__ void key_step(const Lut& L, uint32_t& w0, uint32_t& w
 // children PRF_k(0), PRF_k(1).  The round keys are produced on the fly and
 // shared; after the first AddRoundKey the blocks differ only in byte 0, so
 // round 1 changes only column 0 of the second block.
+//
+// FULL = false computes only bit 0 of each output (what a leaf contributes):
+// byte 0 of the last round reads only byte 0 of column 0 of round 9, and
+// needs only byte 0 of the last round key; o0.x, o1.x then hold that bit in
+// bit 0 and nothing else is defined.
+template <bool FULL>
 __device__ __forceinline__ void prf_pair(const Lut& L, u32x4 k, u32x4& o0, u32x4& o1) {
     uint32_t w0 = k.x, w1 = k.y, w2 = k.z, w3 = k.w;
     uint32_t a0 = w0, a1 = w1, a2 = w2, a3 = w3;
@@ -236,6 +244,16 @@ __device__ __forceinline__ void prf_pair(const Lut& L, u32x4 k, u32x4& o0, u32x4
     PIR_AES_ROUND(6)
     PIR_AES_ROUND(7)
     PIR_AES_ROUND(8)
+    if (!FULL) {
+        key_step<9>(L, w0, w1, w2, w3);
+        const uint32_t s0 = mix_col(L, a0, a1, a2, a3, w0), r0 = mix_col(L, b0, b1, b2, b3, w0);
+        // last round, byte 0 of column 0: S(s0.0) ^ w0.0 ^ S(w3.1) ^ rcon(10); S(x) is byte 1 of a
+        // table entry, so bit 0 of the result sits at bit 8 below
+        const uint32_t kx = L.t<1>(w3) ^ (w0 << 8) ^ (rcon(10) << 8);
+        o0.x = (L.t<0>(s0) ^ kx) >> 8;
+        o1.x = (L.t<0>(r0) ^ kx) >> 8;
+        return;
+    }
     PIR_AES_ROUND(9)
 #undef PIR_AES_ROUND
     key_step<10>(L, w0, w1, w2, w3);
@@ -250,7 +268,7 @@ __device__ __forceinline__ void prf_pair(const Lut& L, u32x4 k, u32x4& o0, u32x4
 __device__ __forceinline__ void expand(const Lut& L, const u32x4* __restrict__ kq, uint32_t n1, uint32_t d, u32x4 r,
                                        u32x4& c0, u32x4& c1) {
     u32x4 g0, g1;
-    prf_pair(L, r, g0, g1);
+    prf_pair<true>(L, r, g0, g1);
     const u32x4 z0 = kq[d], z1 = kq[n1 + d];               // C0[0][d], C0[1][d]
     const u32x4 o0 = kq[2 * n1 + d], o1 = kq[3 * n1 + d];  // C1[0][d], C1[1][d]
     const uint32_t m = 0u - (r.x & 1u);
@@ -259,24 +277,35 @@ __device__ __forceinline__ void expand(const Lut& L, const u32x4* __restrict__ k
     c1 = g1 ^ z1 ^ (mm & (z1 ^ o1));
 }
 
+// Bit 0 of both children of node r at the leaf level d = n (eq. 3 on bit 0).
+__device__ __forceinline__ uint32_t expand_leaf_bits(const Lut& L, const u32x4* __restrict__ kq, uint32_t n1,
+                                                     uint32_t d, u32x4 r) {
+    u32x4 g0, g1;
+    prf_pair<false>(L, r, g0, g1);
+    const uint32_t t = r.x & 1u;
+    const uint32_t z0 = t ? kq[2 * n1 + d].x : kq[d].x;       // C_t[0][d]
+    const uint32_t z1 = t ? kq[3 * n1 + d].x : kq[n1 + d].x;  // C_t[1][d]
+    return ((g0.x ^ z0) & 1u) | (((g1.x ^ z1) & 1u) << 1);
+}
+
 // Expand node i of level a (key blockIdx.y) by E levels (0 <= E <= 5).
 // BITS: write the 2^E leaf bits (E = 5, or a = 0 for domains of at most 32
 // leaves) as word i of the key's selection row.  Otherwise write the 2^E
 // nodes of level a+E at positions (i << E) .. of the key's output row.
-template <bool BITS>
-__global__ void __launch_bounds__(kDpfBlock)
+template <int BS, bool BITS>
+__global__ void __launch_bounds__(BS)
 k_dpf_expand(const uint8_t* __restrict__ keys, uint32_t key_bytes, uint32_t n, uint32_t a, uint32_t E,
              uint64_t count, const u32x4* __restrict__ in, uint64_t in_stride, u32x4* __restrict__ out_nodes,
              uint64_t out_stride, uint32_t* __restrict__ out_bits, uint64_t bits_stride) {
-    // the table is the kernel's only LDS object, at address 0, so a lookup's
-    // LDS address is the v_perm_b32 result itself
+    // the table is the kernel's only LDS object, at address 0, so a
+    // lookup's LDS address is the v_perm_b32 result itself
     __shared__ uint32_t s_tab[kTabBytes / 4];
-    for (uint32_t m = threadIdx.x; m < kTabBytes / 16; m += kDpfBlock) {
+    for (uint32_t m = threadIdx.x; m < kTabBytes / 16; m += BS) {
         const uint32_t v = c_te0[m >> 4];
         reinterpret_cast<u32x4*>(s_tab)[m] = u32x4{v, v, v, v};
     }
     __syncthreads();
-    const uint64_t i = (uint64_t)blockIdx.x * kDpfBlock + threadIdx.x;
+    const uint64_t i = (uint64_t)blockIdx.x * BS + threadIdx.x;
     if (i >= count) return;
     const uint32_t q = blockIdx.y;
     const u32x4* kq = reinterpret_cast<const u32x4*>(keys + (uint64_t)q * key_bytes);
@@ -290,12 +319,14 @@ k_dpf_expand(const uint8_t* __restrict__ keys, uint32_t key_bytes, uint32_t n, u
     const uint32_t total = (1u << E) - 1u;
     u32x4* orow = BITS ? nullptr : out_nodes + q * out_stride + (i << E);
     for (uint32_t k = 0; k < total; ++k) {
+        const bool last = depth + 1 == E;  // the children are outputs
         u32x4 c0, c1;
-        expand(L, kq, n1, a + depth + 1, cur, c0, c1);
-        if (depth + 1 == E) {  // the children are outputs
-            if (BITS)
-                word |= ((c0.x & 1u) | ((c1.x & 1u) << 1)) << (2 * p);
-            else {
+        if (BITS && last)
+            word |= expand_leaf_bits(L, kq, n1, a + E, cur) << (2 * p);
+        else
+            expand(L, kq, n1, a + depth + 1, cur, c0, c1);
+        if (last) {
+            if (!BITS) {
                 orow[2 * p] = c0;
                 orow[2 * p + 1] = c1;
             }
@@ -364,6 +395,18 @@ uint64_t dpf_scratch_nodes(uint32_t n, uint64_t n_leaves) {
     return ceil_shift(n_leaves, 5) + 32;
 }
 
+template <int BS>
+static void launch_step(bool bits, dim3 grid, hipStream_t s, const uint8_t* d_keys, uint32_t kb, uint32_t n,
+                        uint32_t a, uint32_t E, uint64_t count, const u32x4* in, uint64_t in_stride, u32x4* out,
+                        uint64_t out_stride, uint32_t* d_sel, uint64_t stride_words) {
+    if (bits)
+        hipLaunchKernelGGL((k_dpf_expand<BS, true>), grid, dim3(BS), 0, s, d_keys, kb, n, a, E, count, in, in_stride,
+                           nullptr, 0, d_sel, stride_words);
+    else
+        hipLaunchKernelGGL((k_dpf_expand<BS, false>), grid, dim3(BS), 0, s, d_keys, kb, n, a, E, count, in,
+                           in_stride, out, out_stride, nullptr, 0);
+}
+
 hipError_t launch_dpf_eval(int device, const uint8_t* d_keys, uint32_t n, uint32_t n_keys, uint64_t n_leaves,
                            uint32_t* d_sel, uint64_t stride_words, void* scratch, uint64_t scratch_nodes,
                            hipStream_t s) {
@@ -380,17 +423,18 @@ hipError_t launch_dpf_eval(int device, const uint8_t* d_keys, uint32_t n, uint32
     for (int k = 0; k < ns; ++k) {
         const uint32_t a = steps[k][0], E = steps[k][1];
         const uint64_t count = ceil_shift(n_leaves, n - a);
-        const dim3 grid((uint32_t)((count + kDpfBlock - 1) / kDpfBlock), n_keys);
-        if (k + 1 < ns) {
-            u32x4* out = buf[k & 1];
-            hipLaunchKernelGGL(k_dpf_expand<false>, grid, dim3(kDpfBlock), 0, s, d_keys, kb, n, a, E, count,
-                               in, scratch_nodes, out, scratch_nodes, nullptr, 0);
-            in = out;
-        } else {
-            hipLaunchKernelGGL(k_dpf_expand<true>, grid, dim3(kDpfBlock), 0, s, d_keys, kb, n, a, E, count,
-                               in, scratch_nodes, nullptr, 0, d_sel, stride_words);
-        }
+        const bool bits = k + 1 == ns;
+        u32x4* out = bits ? nullptr : buf[k & 1];
+        // large launches: 1024-thread workgroups, one per CU, share one table
+        // copy between 16 waves; small ones: 256 threads, spread over more CUs
+        if (count * n_keys >= kDpfBigLaunch)
+            launch_step<1024>(bits, dim3((uint32_t)((count + 1023) / 1024), n_keys), s, d_keys, kb, n, a, E, count, in,
+                              scratch_nodes, out, scratch_nodes, d_sel, stride_words);
+        else
+            launch_step<256>(bits, dim3((uint32_t)((count + 255) / 256), n_keys), s, d_keys, kb, n, a, E, count, in,
+                             scratch_nodes, out, scratch_nodes, d_sel, stride_words);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (!bits) in = out;
     }
     return hipSuccess;
 }

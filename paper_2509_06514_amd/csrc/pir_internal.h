@@ -74,7 +74,7 @@ hipError_t launch_unslice(const Geometry& g, const uint32_t* src_block0, uint64_
                           uint64_t nrec, hipStream_t s);
 
 // DPF (pir_dpf.hip).
-constexpr uint32_t kDpfBlock = 256;  // threads per workgroup of the expansion kernels
+constexpr uint64_t kDpfBigLaunch = 256 * 1024;  // threads from which DPF launches use 1024-thread workgroups
 uint64_t dpf_key_bytes(uint32_t n);
 // nodes per key in each of the two scratch buffers of an evaluation
 uint64_t dpf_scratch_nodes(uint32_t n, uint64_t n_leaves);
