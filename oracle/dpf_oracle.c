@@ -31,6 +31,10 @@
  *      - C1[x][d] (d = 1..n) is the level-d correction word for child x,
  *        identical in both keys; C1[x][0] is zero.
  *    The two root seeds are inputs (the caller draws them).
+ *    Byte compatibility of these keys with the construction the paper cites
+ *    is parity unpinned (that work's code is not available here); what the
+ *    tests pin is the point-function identity for every key this produces,
+ *    and eq. 1-3 for arbitrary codewords (AESAVS known answers).
  *
  * Built with: gcc -O2 -std=c11 -fPIC -shared.
  */

@@ -83,3 +83,79 @@ def test_key_layout_and_share_density():
     v0 = oracle.dpf_eval_full(k0, n)
     frac = np.unpackbits(v0).mean()
     assert 0.48 < frac < 0.52
+
+
+def _keysbox():
+    out = []
+    for line in open(os.path.join(ROOT, "tests", "golden", "aesavs_keysbox128.txt")):
+        line = line.split("#", 1)[0].strip()
+        if line:
+            k, c = (x.strip() for x in line.split("=", 1))
+            out.append((np.frombuffer(bytes.fromhex(k), np.uint8), np.frombuffer(bytes.fromhex(c), np.uint8)))
+    return out
+
+
+def test_aesavs_keysbox_vectors():
+    z = np.zeros(16, np.uint8)
+    for k, c in _keysbox():
+        assert np.array_equal(oracle.aes128_encrypt(k, z), c)
+
+
+def _blank_key(n):
+    return np.zeros(oracle.dpf_key_bytes(n), np.uint8)
+
+
+def _put(key, n, cw, x, d, block):
+    o = ((2 * cw + x) * (n + 1) + d) * 16
+    key[o:o + 16] = block
+
+
+def test_eval_one_step_at_known_answers():
+    # eq. 2-3 at n = 1, leaf 0: R(1, 0) = AES_{C0[0,0]}(0^128) XOR C_t[0][1],
+    # t = bit 0 of the root; the AES value is a published known answer, the
+    # codeword blocks are arbitrary
+    cws = synth.stream_bytes(synth.S_KEY + 77, 4 * 16).reshape(4, 16)
+    ts = set()
+    for root, ct in _keysbox():
+        key = _blank_key(1)
+        _put(key, 1, 0, 0, 0, root)
+        for i, (cw, x) in enumerate(((0, 0), (0, 1), (1, 0), (1, 1))):
+            _put(key, 1, cw, x, 1, cws[i])
+        t = int(root[0]) & 1
+        ts.add(t)
+        want = ct ^ cws[2 * t]  # C_t[0][1]
+        assert np.array_equal(oracle.dpf_eval_block(key, 1, 0), want)
+        assert oracle.dpf_eval_bit(key, 1, 0) == int(want[0]) & 1
+    assert ts == {0, 1}
+
+
+def test_eval_chain_through_known_answers():
+    # n = 3, leaf 0: choose the correction words so that R(1, 0) and R(2, 0)
+    # are themselves known-answer keys; then R(3, 0) is fixed by a third
+    # known answer.  Pins that each node value keys the next PRF (eq. 3).
+    ks = _keysbox()
+    (k1, c1), (k2, c2), (k3, c3) = ks[0], ks[5], ks[9]
+    n = 3
+    key = _blank_key(n)
+    _put(key, n, 0, 0, 0, k1)
+    t1 = int(k1[0]) & 1
+    _put(key, n, t1, 0, 1, c1 ^ k2)       # R(1,0) = c1 ^ (c1 ^ k2) = k2
+    t2 = int(k2[0]) & 1
+    _put(key, n, t2, 0, 2, c2 ^ k3)       # R(2,0) = k3
+    t3 = int(k3[0]) & 1
+    last = synth.stream_bytes(synth.S_KEY + 78, 16)
+    _put(key, n, t3, 0, 3, last)
+    assert np.array_equal(oracle.dpf_eval_block(key, n, 0), c3 ^ last)
+
+
+def test_point_function_zero_and_large_domain():
+    # n = 0: the two roots differ exactly in bit 0 (eq. 2)
+    k0, k1 = oracle.dpf_gen(0, 0, *_roots(3))
+    assert oracle.dpf_eval_bit(k0, 0, 0) ^ oracle.dpf_eval_bit(k1, 0, 0) == 1
+    # n = 20: sampled leaves, alpha included
+    n = 20
+    rng = np.random.default_rng(20)
+    for alpha in (0, (1 << n) - 1, int(rng.integers(0, 1 << n))):
+        k0, k1 = oracle.dpf_gen(alpha, n, *_roots(4000 + alpha % 97))
+        for x in [alpha] + [int(v) for v in rng.integers(0, 1 << n, 40)]:
+            assert oracle.dpf_eval_bit(k0, n, x) ^ oracle.dpf_eval_bit(k1, n, x) == int(x == alpha), (alpha, x)
