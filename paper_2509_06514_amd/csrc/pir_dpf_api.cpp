@@ -14,13 +14,16 @@ constexpr uint64_t kSelScratchBudget = 2ull << 30;   // selection rows of the ke
 
 uint64_t words_for(uint64_t n_leaves) { return (n_leaves + 31) / 32; }
 
-// Keys per group so the node scratch stays within budget (at least one).
+// Keys per group so the node scratch stays within budget (at least one key),
+// balanced so the groups differ in size by at most one.
 uint32_t keys_per_group(uint32_t n, uint64_t n_leaves, uint32_t n_keys) {
     const uint64_t per_key = 2 * dpf_scratch_nodes(n, n_leaves) * 16;
     if (per_key == 0) return n_keys;
     uint64_t g = kNodeScratchBudget / per_key;
     if (g < 1) g = 1;
-    return g < n_keys ? (uint32_t)g : n_keys;
+    if (g >= n_keys) return n_keys;
+    const uint64_t groups = (n_keys + g - 1) / g;
+    return (uint32_t)((n_keys + groups - 1) / groups);
 }
 
 // Grow a per-stream buffer; waits for the stream first if it is in use.
