@@ -227,6 +227,8 @@ typedef struct pir_serve_stats {
     uint64_t h2d_bytes;       /* selection bytes uploaded */
     uint32_t max_inflight;    /* most slots busy at once (batches overlapping on the device) */
     uint32_t n_slots;
+    uint64_t key_requests;    /* requests submitted as DPF keys */
+    uint64_t updates_applied; /* record updates applied */
 } pir_serve_stats;
 
 int pir_serve_create(pir_ctx* ctx, const pir_serve_config* cfg, pir_server** out);
@@ -242,6 +244,31 @@ int pir_serve_add_db(pir_server* srv, pir_db* db, uint32_t* db_id);
  * PIR_E_BUSY (queue full), PIR_E_SHUTDOWN.
  */
 int pir_serve_submit(pir_server* srv, uint32_t db_id, const uint8_t* sel_bits, uint8_t* out,
+                     uint64_t* ticket);
+
+/*
+ * Queue one query as a DPF key (IM-PIR Sec. 3.2): the server evaluates it
+ * over the database's domain (n = pir_dpf_domain_bits(N)) and answers with
+ * XOR_j Eval(key, j) * D[j].  key (pir_dpf_key_bytes(n) bytes, layout as in
+ * the DPF section below) is copied before the call returns; out (R bytes)
+ * must stay valid until completion.  Key requests are batched separately
+ * from selection requests.  Errors as pir_serve_submit.
+ */
+int pir_serve_submit_key(pir_server* srv, uint32_t db_id, const uint8_t* key, uint8_t* out,
+                         uint64_t* ticket);
+
+/*
+ * Replace records [first, first + count) of a served database (the paper
+ * applies database updates in idle windows, on a stable version: Sec. 3.3).
+ * The records (count * R bytes, row-major) are copied before the call
+ * returns.  The update is ordered with the database's requests: every
+ * request submitted before it is answered from the old records, every
+ * request submitted after it from the new ones; it is applied once the
+ * earlier requests have completed, and later requests wait for it.  The
+ * ticket completes (pir_serve_wait / pir_serve_poll) when the records are in
+ * place.  Errors: PIR_E_INVAL (range), PIR_E_NOTFOUND, PIR_E_SHUTDOWN.
+ */
+int pir_serve_update(pir_server* srv, uint32_t db_id, uint64_t first, uint64_t count, const void* records,
                      uint64_t* ticket);
 
 /* Wait for a ticket: PIR_OK once out holds the answer, the request's own
@@ -321,6 +348,13 @@ int pir_dpf_eval_async(pir_ctx* ctx, const void* d_keys, uint32_t n, uint32_t n_
  * asynchronous on hip_stream, with the same workspace rules.
  */
 int pir_dpf_dpxor_async(pir_db* db, const void* d_keys, uint32_t n_keys, void* d_out, void* hip_stream);
+
+/*
+ * Client side, host only: the record from the two servers' answers
+ * (Algorithm 1, client step: D[i] = r1 XOR r2).  out may alias either
+ * input.  Errors: PIR_E_INVAL for NULL pointers.
+ */
+int pir_reconstruct(const uint8_t* ans0, const uint8_t* ans1, uint64_t record_bytes, uint8_t* out);
 
 /* ---------------------------------------------------------------- memory */
 

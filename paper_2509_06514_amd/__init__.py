@@ -13,7 +13,7 @@ from ._native import (PIR_MAX_BATCH, PIR_VARIANT_AUTO, PIR_VARIANT_MFMA_F4, PIR_
                       PIR_VARIANT_VALU, PirError, check, lib)
 
 __all__ = ["Context", "Database", "Server", "KernelCfg", "PirError", "lib", "sel_stride_for",
-           "dpf_key_bytes", "dpf_domain_bits", "dpf_gen",
+           "dpf_key_bytes", "dpf_domain_bits", "dpf_gen", "reconstruct",
            "PIR_MAX_BATCH", "PIR_VARIANT_AUTO", "PIR_VARIANT_VALU", "PIR_VARIANT_MFMA_I8",
            "PIR_VARIANT_MFMA_F4"]
 
@@ -23,6 +23,8 @@ def _ptr(a):
 
 
 def _u8(a):
+    if isinstance(a, (bytes, bytearray, memoryview)):
+        return np.frombuffer(bytes(a), np.uint8).copy()
     a = np.asarray(a)
     if a.dtype != np.uint8:
         a = a.view(np.uint8) if a.dtype.itemsize == 1 else a.astype(np.uint8)
@@ -73,6 +75,16 @@ def dpf_key_bytes(n):
 def dpf_domain_bits(n_records):
     """Smallest n with 2^n >= n_records."""
     return int(lib().pir_dpf_domain_bits(n_records))
+
+
+def reconstruct(ans0, ans1):
+    """Client side: the record from the two servers' answers (XOR)."""
+    a, b = _u8(ans0).reshape(-1), _u8(ans1).reshape(-1)
+    if a.size != b.size:
+        raise ValueError("answers differ in length")
+    out = np.empty_like(a)
+    check(lib().pir_reconstruct(_ptr(a), _ptr(b), a.size, _ptr(out)), "pir_reconstruct")
+    return out
 
 
 def dpf_gen(alpha, n, root0, root1):
@@ -279,6 +291,25 @@ class Server:
         t = ctypes.c_uint64()
         check(lib().pir_serve_submit(self._h, db_id, _ptr(sel), _ptr(out), ctypes.byref(t)),
               "pir_serve_submit")
+        return t.value
+
+    def submit_key(self, db_id, key, out):
+        """Queue a query as a DPF key (the server evaluates it); `out` is filled on completion."""
+        key = _u8(key).reshape(-1)
+        n = dpf_domain_bits(self._dbs[db_id].n_records)
+        if key.size < dpf_key_bytes(n):
+            raise ValueError("key shorter than pir_dpf_key_bytes(n)")
+        t = ctypes.c_uint64()
+        check(lib().pir_serve_submit_key(self._h, db_id, _ptr(key), _ptr(out), ctypes.byref(t)),
+              "pir_serve_submit_key")
+        return t.value
+
+    def update(self, db_id, first, records):
+        """Queue a record update, ordered with the database's requests; returns its ticket."""
+        records = _u8(records)
+        t = ctypes.c_uint64()
+        check(lib().pir_serve_update(self._h, db_id, first, records.shape[0], _ptr(records), ctypes.byref(t)),
+              "pir_serve_update")
         return t.value
 
     def submit_raw(self, db_id, sel_ptr, out_ptr):

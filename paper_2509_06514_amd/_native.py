@@ -61,7 +61,8 @@ class pir_serve_stats(ctypes.Structure):
                 ("mean_us", ctypes.c_double), ("max_us", ctypes.c_double),
                 ("elapsed_s", ctypes.c_double), ("qps", ctypes.c_double),
                 ("batch_hist", ctypes.c_uint64 * 13), ("h2d_bytes", ctypes.c_uint64),
-                ("max_inflight", ctypes.c_uint32), ("n_slots", ctypes.c_uint32)]
+                ("max_inflight", ctypes.c_uint32), ("n_slots", ctypes.c_uint32),
+                ("key_requests", ctypes.c_uint64), ("updates_applied", ctypes.c_uint64)]
 
 
 _P = ctypes.c_void_p
@@ -93,6 +94,8 @@ SIGNATURES = {
     "pir_serve_create": (_I, [_P, ctypes.POINTER(pir_serve_config), _PP]),
     "pir_serve_add_db": (_I, [_P, _P, ctypes.POINTER(_U32)]),
     "pir_serve_submit": (_I, [_P, _U32, _P, _P, ctypes.POINTER(_U64)]),
+    "pir_serve_submit_key": (_I, [_P, _U32, _P, _P, ctypes.POINTER(_U64)]),
+    "pir_serve_update": (_I, [_P, _U32, _U64, _U64, _P, ctypes.POINTER(_U64)]),
     "pir_serve_wait": (_I, [_P, _U64, _I]),
     "pir_serve_poll": (_I, [_P, _U64, ctypes.POINTER(_I)]),
     "pir_serve_stats_get": (_I, [_P, ctypes.POINTER(pir_serve_stats), _I]),
@@ -102,6 +105,7 @@ SIGNATURES = {
     "pir_dpf_gen": (_I, [_U64, _U32, _P, _P, _P, _P]),
     "pir_dpf_eval_async": (_I, [_P, _P, _U32, _U32, _U64, _P, _U64, _P]),
     "pir_dpf_dpxor_async": (_I, [_P, _P, _U32, _P, _P]),
+    "pir_reconstruct": (_I, [_P, _P, _U64, _P]),
     "pir_host_alloc": (_P, [ctypes.c_size_t]),
     "pir_host_free": (None, [_P]),
 }

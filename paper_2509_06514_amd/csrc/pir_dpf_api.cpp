@@ -38,6 +38,14 @@ int grow(DevBuf& b, size_t need, hipStream_t s, const char* what) {
     return PIR_OK;
 }
 
+}  // namespace
+
+uint64_t dpf_eval_scratch_bytes(uint32_t n, uint64_t n_leaves, uint32_t n_keys) {
+    return (uint64_t)keys_per_group(n, n_leaves, n_keys) * 2 * dpf_scratch_nodes(n, n_leaves) * 16 + 16;
+}
+
+namespace {
+
 // Evaluate n_keys keys into rows of d_sel, in groups bounded by the node
 // scratch budget.  Caller holds no lock; ws belongs to stream s.
 int eval_groups(Ctx* ctx, const uint8_t* d_keys, uint32_t n, uint32_t n_keys, uint64_t n_leaves, uint32_t* d_sel,
@@ -72,6 +80,12 @@ int eval_groups(Ctx* ctx, const uint8_t* d_keys, uint32_t n, uint32_t n_keys, ui
 }
 
 }  // namespace
+
+int dpf_eval_into(Ctx* ctx, const uint8_t* d_keys, uint32_t n, uint32_t n_keys, uint64_t n_leaves, uint32_t* d_sel,
+                  uint64_t stride_words, hipStream_t s) {
+    return eval_groups(ctx, d_keys, n, n_keys, n_leaves, d_sel, stride_words, s);
+}
+
 }  // namespace pir
 
 using namespace pir;
@@ -93,6 +107,13 @@ int pir_dpf_gen(uint64_t alpha, uint32_t n, const uint8_t* root0, const uint8_t*
     if (n > 62) return fail(PIR_E_INVAL, "pir_dpf_gen: n=%u > 62", n);
     if (alpha >> n) return fail(PIR_E_INVAL, "pir_dpf_gen: alpha outside [0, 2^%u)", n);
     dpf_gen_host(alpha, n, root0, root1, key0, key1);
+    return PIR_OK;
+}
+
+int pir_reconstruct(const uint8_t* ans0, const uint8_t* ans1, uint64_t record_bytes, uint8_t* out) {
+    clear_error();
+    if (!ans0 || !ans1 || !out) return fail(PIR_E_INVAL, "pir_reconstruct: NULL argument");
+    for (uint64_t i = 0; i < record_bytes; ++i) out[i] = ans0[i] ^ ans1[i];
     return PIR_OK;
 }
 

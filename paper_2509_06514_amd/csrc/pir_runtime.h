@@ -103,6 +103,13 @@ struct Ctx {
 };
 
 int finish_plan(const Geometry& g, uint32_t q, Plan& p);
+
+// DPF evaluation of n_keys device keys into selection rows on stream s, with
+// the stream's node scratch (pir_dpf_api.cpp); and the most scratch that
+// call may allocate.
+int dpf_eval_into(Ctx* ctx, const uint8_t* d_keys, uint32_t n, uint32_t n_keys, uint64_t n_leaves, uint32_t* d_sel,
+                  uint64_t stride_words, hipStream_t s);
+uint64_t dpf_eval_scratch_bytes(uint32_t n, uint64_t n_leaves, uint32_t n_keys);
 size_t partial_bytes(const Geometry& g, const Plan& p, uint32_t q);
 
 }  // namespace pir

@@ -3,16 +3,23 @@
 // The paper's batching scheme (IM-PIR Sec. 3.4, "Batching client queries")
 // puts expanded queries on a shared task queue and has scheduler threads hand
 // them to DPU clusters as clusters free up.  Here:
-//  - each database has its own queue, held in a pinned host ring of selection
-//    rows (pir_serve_submit copies the caller's bits straight into the ring,
-//    so a batch uploads with one or two host-to-device copies and no extra
-//    host copy);
+//  - each database has its own queues, held in pinned host rings: one of
+//    selection rows (pir_serve_submit copies the caller's bits straight into
+//    the ring, so a batch uploads with one or two host-to-device copies and
+//    no extra host copy) and one of DPF keys (pir_serve_submit_key; the
+//    server evaluates them, Sec. 3.2, so a query crosses PCIe as a key of
+//    64 (n+1) bytes instead of N/8 bytes of bits);
 //  - a slot is the GPU analogue of a cluster: a stream with its own device
-//    selection, answer and scratch buffers; slots run concurrently;
+//    selection, key, answer and scratch buffers; slots run concurrently;
 //  - one scheduler thread retires finished slots (answers to the callers'
 //    buffers, latency recorded) and fills free slots with up to q_max pending
-//    requests of the database whose oldest request has waited longest.
-//    Requests arriving while batches run join the next batches.
+//    requests of one kind of the database whose oldest request has waited
+//    longest.  Requests arriving while batches run join the next batches;
+//  - record updates (pir_serve_update) are barriers in a database's request
+//    order: an update is applied in an idle window of its database, once
+//    every request submitted before it has completed and before any request
+//    submitted after it is dispatched, so every answer comes from one whole
+//    version of the records (the idle-window updates of Sec. 3.3).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,6 +41,8 @@ namespace pir {
 
 using Clock = std::chrono::steady_clock;
 
+enum Kind { kSel = 0, kKey = 1 };
+
 struct Ticket {
     int status = PIR_OK;
     bool done = false;
@@ -41,23 +50,62 @@ struct Ticket {
 
 struct Pending {
     uint64_t ticket;
+    uint64_t seq;  // position in the database's submission order (updates included)
     uint64_t row;  // absolute ring row index
     uint8_t* out;
     Clock::time_point t_submit;
 };
 
-struct DbQueue {
-    Db* db = nullptr;
-    uint64_t dstride = 0;   // device/ring row pitch (bytes)
-    uint64_t row_bytes = 0; // ceil(N/8)
-    HostBuf ring;
-    uint64_t ring_rows = 0;
+// Pinned host ring of fixed-size rows; a row is free again once every batch
+// up to and including it has retired.
+struct Ring {
+    HostBuf buf;
+    uint64_t stride = 0, rows = 0;
     uint64_t next_row = 0;      // next row to fill (absolute)
     uint64_t released_row = 0;  // rows below this are free again (absolute)
-    std::deque<Pending> q;
-    // batches in flight, in dispatch order: [first_row, end_row, done]
     struct Span { uint64_t first, end; bool done; };
-    std::deque<Span> spans;
+    std::deque<Span> spans;     // batches in flight, in dispatch order
+
+    uint64_t free_rows() const { return rows - (next_row - released_row); }
+    uint8_t* row_ptr(uint64_t r) const { return (uint8_t*)buf.ptr + (r % rows) * stride; }
+    void finish(uint64_t first) {
+        for (auto& sp : spans)
+            if (sp.first == first) sp.done = true;
+        while (!spans.empty() && spans.front().done) {
+            released_row = spans.front().end;
+            spans.pop_front();
+        }
+    }
+};
+
+struct UpdateReq {
+    uint64_t ticket, seq, first, count;
+    std::vector<uint8_t> records;
+};
+
+struct DbQueue {
+    Db* db = nullptr;
+    uint64_t dstride = 0;    // device selection row pitch (bytes)
+    uint64_t row_bytes = 0;  // ceil(N/8)
+    uint32_t n_bits = 0;     // DPF domain 2^n_bits
+    uint64_t key_bytes = 0;
+    Ring ring[2];            // kSel: selection rows (pitch dstride); kKey: keys
+    std::deque<Pending> q[2];
+    std::deque<UpdateReq> updates;
+    uint64_t next_seq = 0;
+    uint32_t inflight = 0;   // busy slots on this database
+
+    uint64_t barrier() const { return updates.empty() ? UINT64_MAX : updates.front().seq; }
+    // requests of kind k that may run before the next update, up to `cap`
+    uint32_t eligible(int k, uint32_t cap) const {
+        const uint64_t b = barrier();
+        uint32_t n = 0;
+        for (const Pending& r : q[k]) {
+            if (r.seq >= b || n == cap) break;
+            ++n;
+        }
+        return n;
+    }
 };
 
 struct Slot {
@@ -65,10 +113,11 @@ struct Slot {
     hipEvent_t done_ev = nullptr;
     bool busy = false;
     uint32_t db = 0;
+    int kind = kSel;
     uint64_t span_first = 0;
     std::vector<Pending> reqs;
     HostBuf h_out;
-    DevBuf d_sel, d_out, partials;
+    DevBuf d_sel, d_out, partials, d_keys;
 };
 
 struct Server {
@@ -87,16 +136,21 @@ struct Server {
     // statistics
     std::vector<double> lat_us;
     uint64_t submitted = 0, completed = 0, rejected = 0, batches = 0, h2d_bytes = 0;
+    uint64_t key_requests = 0, updates_applied = 0;
     uint64_t hist[13] = {0};
     uint32_t max_inflight = 0;
     Clock::time_point t0;
 
-    void run();
+    void run(std::unique_lock<std::mutex>& lk);
     bool dispatch_one(Slot& s);
     void retire(Slot& s, int status);
+    bool apply_ready_update(std::unique_lock<std::mutex>& lk);
+    uint64_t new_ticket() {
+        const uint64_t t = next_ticket++;
+        tickets[t] = Ticket{};
+        return t;
+    }
 };
-
-static uint64_t ring_free(const DbQueue& d) { return d.ring_rows - (d.next_row - d.released_row); }
 
 void Server::retire(Slot& s, int status) {
     DbQueue& d = *dbs[s.db];
@@ -112,42 +166,62 @@ void Server::retire(Slot& s, int status) {
         lat_us.push_back(std::chrono::duration<double, std::micro>(now - r.t_submit).count());
         ++completed;
     }
-    for (auto& sp : d.spans)
-        if (sp.first == s.span_first) sp.done = true;
-    while (!d.spans.empty() && d.spans.front().done) {
-        d.released_row = d.spans.front().end;
-        d.spans.pop_front();
-    }
+    d.ring[s.kind].finish(s.span_first);
+    --d.inflight;
     s.reqs.clear();
     s.busy = false;
 }
 
-// Pick the database whose head request is oldest and launch up to q_max of
-// its requests on slot s.  Returns false if nothing is ready.
+// Upload ring rows [first, first + n) to dst (contiguous modulo the ring size).
+static int upload_rows(const Ring& ring, uint64_t first, uint64_t n, void* dst, hipStream_t s) {
+    uint64_t done = 0;
+    while (done < n) {
+        const uint64_t r = (first + done) % ring.rows;
+        const uint64_t k = std::min<uint64_t>(n - done, ring.rows - r);
+        hipError_t e = hipMemcpyAsync((uint8_t*)dst + done * ring.stride, (uint8_t*)ring.buf.ptr + r * ring.stride,
+                                      k * ring.stride, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "request upload");
+        done += k;
+    }
+    return PIR_OK;
+}
+
+// Pick the (database, kind) whose oldest runnable request has waited longest
+// and launch up to q_max of its requests on slot s.  Returns false if nothing
+// is ready.
 bool Server::dispatch_one(Slot& s) {
-    int best = -1;
+    int best = -1, best_k = kSel;
     Clock::time_point best_t{};
     const auto now = Clock::now();
     for (size_t i = 0; i < dbs.size(); ++i) {
         DbQueue& d = *dbs[i];
-        if (d.q.empty()) continue;
-        const bool full = d.q.size() >= cfg.q_max;
-        const double age_us = std::chrono::duration<double, std::micro>(now - d.q.front().t_submit).count();
-        if (!full && !stopping && cfg.max_wait_us && age_us < cfg.max_wait_us) continue;
-        if (best < 0 || d.q.front().t_submit < best_t) {
-            best = (int)i;
-            best_t = d.q.front().t_submit;
+        for (int k = 0; k < 2; ++k) {
+            const uint32_t ready = d.eligible(k, cfg.q_max);
+            if (ready == 0) continue;
+            const bool full = ready >= cfg.q_max;
+            const Pending& head = d.q[k].front();
+            const double age_us = std::chrono::duration<double, std::micro>(now - head.t_submit).count();
+            // a pending update closes the batch: what precedes it runs now
+            const bool closed = !d.updates.empty();
+            if (!full && !closed && !stopping && cfg.max_wait_us && age_us < cfg.max_wait_us) continue;
+            if (best < 0 || head.t_submit < best_t) {
+                best = (int)i;
+                best_k = k;
+                best_t = head.t_submit;
+            }
         }
     }
     if (best < 0) return false;
     DbQueue& d = *dbs[best];
     const Geometry& g = d.db->geo;
-    const uint32_t n = (uint32_t)std::min<size_t>(d.q.size(), cfg.q_max);
-    s.reqs.assign(d.q.begin(), d.q.begin() + n);
-    d.q.erase(d.q.begin(), d.q.begin() + n);
+    const uint32_t n = d.eligible(best_k, cfg.q_max);
+    s.reqs.assign(d.q[best_k].begin(), d.q[best_k].begin() + n);
+    d.q[best_k].erase(d.q[best_k].begin(), d.q[best_k].begin() + n);
     s.db = (uint32_t)best;
+    s.kind = best_k;
     s.span_first = s.reqs.front().row;
-    d.spans.push_back({s.reqs.front().row, s.reqs.back().row + 1, false});
+    d.ring[best_k].spans.push_back({s.reqs.front().row, s.reqs.back().row + 1, false});
+    ++d.inflight;
     ++batches;
     uint32_t bin = 0;
     while ((2u << bin) <= n && bin < 12) ++bin;
@@ -160,25 +234,25 @@ bool Server::dispatch_one(Slot& s) {
         if ((e = s.d_sel.ensure(d.dstride * cfg.q_max)) != hipSuccess ||
             (e = s.d_out.ensure((size_t)g.R * cfg.q_max)) != hipSuccess ||
             (e = s.h_out.ensure((size_t)g.R * cfg.q_max)) != hipSuccess ||
-            (e = s.partials.ensure(partial_bytes(g, p, n))) != hipSuccess)
+            (e = s.partials.ensure(partial_bytes(g, p, n))) != hipSuccess ||
+            (best_k == kKey && (e = s.d_keys.ensure(d.key_bytes * cfg.q_max)) != hipSuccess))
             rc = hip_fail(e, "serving slot buffers");
     }
-    // upload the batch's ring rows (contiguous modulo the ring size)
     const uint64_t first = s.reqs.front().row;
-    uint64_t done_rows = 0;
-    while (rc == PIR_OK && done_rows < n) {
-        const uint64_t r = (first + done_rows) % d.ring_rows;
-        const uint64_t k = std::min<uint64_t>(n - done_rows, d.ring_rows - r);
-        e = hipMemcpyAsync((uint8_t*)s.d_sel.ptr + done_rows * d.dstride, (uint8_t*)d.ring.ptr + r * d.dstride,
-                           k * d.dstride, hipMemcpyHostToDevice, s.stream);
-        if (e != hipSuccess) rc = hip_fail(e, "selection upload");
-        done_rows += k;
-    }
-    if (rc == PIR_OK) {
+    if (rc == PIR_OK && best_k == kSel) {
+        rc = upload_rows(d.ring[kSel], first, n, s.d_sel.ptr, s.stream);
         h2d_bytes += (uint64_t)n * d.dstride;
+    } else if (rc == PIR_OK) {
+        // keys: upload, then evaluate into the slot's selection rows
+        rc = upload_rows(d.ring[kKey], first, n, s.d_keys.ptr, s.stream);
+        h2d_bytes += (uint64_t)n * d.key_bytes;
+        if (rc == PIR_OK)
+            rc = dpf_eval_into(ctx, (const uint8_t*)s.d_keys.ptr, d.n_bits, n, g.n, (uint32_t*)s.d_sel.ptr,
+                               d.dstride / 4, s.stream);
+    }
+    if (rc == PIR_OK)
         rc = ctx->enqueue_scan(*d.db, p, (const uint32_t*)s.d_sel.ptr, d.dstride / 4, n, (uint8_t*)s.d_out.ptr,
                                (uint8_t*)s.partials.ptr, s.stream);
-    }
     if (rc == PIR_OK) {
         e = hipMemcpyAsync(s.h_out.ptr, s.d_out.ptr, (size_t)g.R * n, hipMemcpyDeviceToHost, s.stream);
         if (e == hipSuccess) e = hipEventRecord(s.done_ev, s.stream);
@@ -198,9 +272,33 @@ bool Server::dispatch_one(Slot& s) {
     return true;
 }
 
-void Server::run() {
+// Apply the first pending update of a database that has reached its idle
+// window (nothing before it queued or in flight).  The lock is released while
+// the records are written; only this thread dispatches, so nothing of that
+// database starts meanwhile.  Returns true if an update was applied.
+bool Server::apply_ready_update(std::unique_lock<std::mutex>& lk) {
+    for (auto& dp : dbs) {
+        DbQueue& d = *dp;
+        if (d.updates.empty() || d.inflight || d.eligible(kSel, 1) || d.eligible(kKey, 1)) continue;
+        UpdateReq& u = d.updates.front();
+        lk.unlock();
+        const int rc = pir_db_update(reinterpret_cast<pir_db*>(d.db), u.first, u.count, u.records.data());
+        lk.lock();
+        auto it = tickets.find(u.ticket);
+        if (it != tickets.end()) {
+            it->second.status = rc;
+            it->second.done = true;
+        }
+        if (rc == PIR_OK) ++updates_applied;
+        d.updates.pop_front();
+        cv_done.notify_all();
+        return true;
+    }
+    return false;
+}
+
+void Server::run(std::unique_lock<std::mutex>& lk) {
     (void)ctx->bind();
-    std::unique_lock<std::mutex> lk(mu);
     for (;;) {
         bool any_busy = false, progressed = false;
         for (auto& sp : slots) {
@@ -219,17 +317,19 @@ void Server::run() {
             }
         }
         if (progressed) cv_done.notify_all();
-        bool waiting_batches = false;
+        while (apply_ready_update(lk)) {
+        }
         for (auto& sp : slots) {
             Slot& s = *sp;
             if (s.busy) continue;
             if (!dispatch_one(s)) break;
             any_busy = any_busy || s.busy;
         }
+        bool waiting = false;
         for (auto& d : dbs)
-            if (!d->q.empty()) waiting_batches = true;
-        if (stopping && !waiting_batches && !any_busy) break;
-        if (any_busy || waiting_batches) {
+            if (!d->q[kSel].empty() || !d->q[kKey].empty() || !d->updates.empty()) waiting = true;
+        if (stopping && !waiting && !any_busy) break;
+        if (any_busy || waiting) {
             // poll slot completion (and max_wait deadlines) at a short interval
             cv_sched.wait_for(lk, std::chrono::microseconds(20));
         } else {
@@ -275,7 +375,10 @@ int pir_serve_create(pir_ctx* c, const pir_serve_config* cfg, pir_server** out) 
     }
     srv->t0 = Clock::now();
     Server* raw = srv.get();
-    raw->th = std::thread([raw] { raw->run(); });
+    raw->th = std::thread([raw] {
+        std::unique_lock<std::mutex> lk(raw->mu);
+        raw->run(lk);
+    });
     *out = reinterpret_cast<pir_server*>(srv.release());
     return PIR_OK;
 }
@@ -291,12 +394,16 @@ int pir_serve_add_db(pir_server* sv, pir_db* d, uint32_t* db_id) {
     dq->db = db;
     dq->row_bytes = (g.n + 7) / 8;
     dq->dstride = (4ull * g.nb + 255) / 256 * 256;
-    // slot buffers this database may need: selections, answers, scratch
+    dq->n_bits = pir_dpf_domain_bits(g.n);
+    dq->key_bytes = dpf_key_bytes(dq->n_bits);
+    // slot buffers this database may need: selections, keys, answers, scratch,
+    // DPF evaluation scratch
     Plan p;
     int rc = srv->ctx->plan_for(*db, srv->cfg.q_max, nullptr, p);
     if (rc) return rc;
-    const uint64_t slot_bytes = dq->dstride * srv->cfg.q_max + (uint64_t)g.R * srv->cfg.q_max +
-                                partial_bytes(g, p, srv->cfg.q_max);
+    const uint64_t slot_bytes = dq->dstride * srv->cfg.q_max + dq->key_bytes * srv->cfg.q_max +
+                                (uint64_t)g.R * srv->cfg.q_max + partial_bytes(g, p, srv->cfg.q_max) +
+                                dpf_eval_scratch_bytes(dq->n_bits, g.n, srv->cfg.q_max);
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->stopping) return fail(PIR_E_SHUTDOWN, "server is shutting down");
     const uint64_t need = g.bytes() + slot_bytes * srv->cfg.n_slots;
@@ -304,13 +411,20 @@ int pir_serve_add_db(pir_server* sv, pir_db* d, uint32_t* db_id) {
         return fail(PIR_E_NOMEM, "admitting this database needs %llu bytes; %llu of the %llu-byte budget are taken",
                     (unsigned long long)need, (unsigned long long)srv->admitted_bytes,
                     (unsigned long long)srv->cfg.hbm_budget_bytes);
-    // pinned request ring: up to 256 MiB, at least 2 batches, at most queue_cap rows
-    uint64_t rows = std::max<uint64_t>(2ull * srv->cfg.q_max, (256ull << 20) / dq->dstride);
-    rows = std::min<uint64_t>(rows, std::max<uint64_t>(srv->cfg.queue_cap, srv->cfg.q_max));
-    hipError_t e = dq->ring.ensure(rows * dq->dstride);
-    if (e != hipSuccess) return hip_fail(e, "pinned request ring");
-    memset(dq->ring.ptr, 0, rows * dq->dstride);
-    dq->ring_rows = rows;
+    // pinned request rings: selections up to 256 MiB, keys up to 16 MiB; at
+    // least 2 batches each, at most queue_cap rows
+    const uint64_t cap_rows = std::max<uint64_t>(srv->cfg.queue_cap, srv->cfg.q_max);
+    const uint64_t strides[2] = {dq->dstride, dq->key_bytes};
+    const uint64_t budgets[2] = {256ull << 20, 16ull << 20};
+    for (int k = 0; k < 2; ++k) {
+        uint64_t rows = std::max<uint64_t>(2ull * srv->cfg.q_max, budgets[k] / strides[k]);
+        rows = std::min<uint64_t>(rows, cap_rows);
+        hipError_t e = dq->ring[k].buf.ensure(rows * strides[k]);
+        if (e != hipSuccess) return hip_fail(e, "pinned request ring");
+        memset(dq->ring[k].buf.ptr, 0, rows * strides[k]);
+        dq->ring[k].rows = rows;
+        dq->ring[k].stride = strides[k];
+    }
     srv->admitted_bytes += need;
     *db_id = (uint32_t)srv->dbs.size();
     srv->dbs.push_back(std::move(dq));
@@ -329,18 +443,71 @@ int pir_serve_submit(pir_server* sv, uint32_t db_id, const uint8_t* sel_bits, ui
     if (srv->failed) return fail(PIR_E_DEVICE, "server stopped after a device error");
     if (db_id >= srv->dbs.size()) return fail(PIR_E_NOTFOUND, "unknown database id %u", db_id);
     DbQueue& d = *srv->dbs[db_id];
-    if (d.q.size() >= srv->cfg.queue_cap || ring_free(d) == 0) {
+    if (d.q[kSel].size() >= srv->cfg.queue_cap || d.ring[kSel].free_rows() == 0) {
         ++srv->rejected;
         return fail(PIR_E_BUSY, "queue of database %u is full", db_id);
     }
-    const uint64_t row = d.next_row++;
-    uint8_t* dst = (uint8_t*)d.ring.ptr + (row % d.ring_rows) * d.dstride;
-    memcpy(dst, sel_bits, d.row_bytes);
-    const uint64_t t = srv->next_ticket++;
-    srv->tickets[t] = Ticket{};
-    d.q.push_back({t, row, out, Clock::now()});
+    const uint64_t row = d.ring[kSel].next_row++;
+    memcpy(d.ring[kSel].row_ptr(row), sel_bits, d.row_bytes);
+    const uint64_t t = srv->new_ticket();
+    d.q[kSel].push_back({t, d.next_seq++, row, out, Clock::now()});
     ++srv->submitted;
     *ticket = t;
+    lk.unlock();
+    srv->cv_sched.notify_one();
+    return PIR_OK;
+}
+
+int pir_serve_submit_key(pir_server* sv, uint32_t db_id, const uint8_t* key, uint8_t* out, uint64_t* ticket) {
+    clear_error();
+    if (!sv || !key || !out || !ticket) return fail(PIR_E_INVAL, "pir_serve_submit_key: NULL argument");
+    Server* srv = reinterpret_cast<Server*>(sv);
+    std::unique_lock<std::mutex> lk(srv->mu);
+    if (srv->stopping) {
+        ++srv->rejected;
+        return fail(PIR_E_SHUTDOWN, "server is shutting down");
+    }
+    if (srv->failed) return fail(PIR_E_DEVICE, "server stopped after a device error");
+    if (db_id >= srv->dbs.size()) return fail(PIR_E_NOTFOUND, "unknown database id %u", db_id);
+    DbQueue& d = *srv->dbs[db_id];
+    if (d.q[kKey].size() >= srv->cfg.queue_cap || d.ring[kKey].free_rows() == 0) {
+        ++srv->rejected;
+        return fail(PIR_E_BUSY, "key queue of database %u is full", db_id);
+    }
+    const uint64_t row = d.ring[kKey].next_row++;
+    memcpy(d.ring[kKey].row_ptr(row), key, d.key_bytes);
+    const uint64_t t = srv->new_ticket();
+    d.q[kKey].push_back({t, d.next_seq++, row, out, Clock::now()});
+    ++srv->submitted;
+    ++srv->key_requests;
+    *ticket = t;
+    lk.unlock();
+    srv->cv_sched.notify_one();
+    return PIR_OK;
+}
+
+int pir_serve_update(pir_server* sv, uint32_t db_id, uint64_t first, uint64_t count, const void* records,
+                     uint64_t* ticket) {
+    clear_error();
+    if (!sv || !records || !ticket) return fail(PIR_E_INVAL, "pir_serve_update: NULL argument");
+    Server* srv = reinterpret_cast<Server*>(sv);
+    std::unique_lock<std::mutex> lk(srv->mu);
+    if (srv->stopping) return fail(PIR_E_SHUTDOWN, "server is shutting down");
+    if (srv->failed) return fail(PIR_E_DEVICE, "server stopped after a device error");
+    if (db_id >= srv->dbs.size()) return fail(PIR_E_NOTFOUND, "unknown database id %u", db_id);
+    DbQueue& d = *srv->dbs[db_id];
+    const Geometry& g = d.db->geo;
+    if (count == 0 || first >= g.n || count > g.n - first)
+        return fail(PIR_E_INVAL, "pir_serve_update: range [%llu, +%llu) outside N=%llu", (unsigned long long)first,
+                    (unsigned long long)count, (unsigned long long)g.n);
+    UpdateReq u;
+    u.first = first;
+    u.count = count;
+    u.records.assign((const uint8_t*)records, (const uint8_t*)records + count * g.R);
+    u.ticket = srv->new_ticket();
+    u.seq = d.next_seq++;
+    *ticket = u.ticket;
+    d.updates.push_back(std::move(u));
     lk.unlock();
     srv->cv_sched.notify_one();
     return PIR_OK;
@@ -392,6 +559,8 @@ int pir_serve_stats_get(pir_server* sv, pir_serve_stats* out, int reset) {
     for (int i = 0; i < 13; ++i) out->batch_hist[i] = srv->hist[i];
     out->max_inflight = srv->max_inflight;
     out->n_slots = (uint32_t)srv->slots.size();
+    out->key_requests = srv->key_requests;
+    out->updates_applied = srv->updates_applied;
     out->elapsed_s = std::chrono::duration<double>(Clock::now() - srv->t0).count();
     out->qps = out->elapsed_s > 0 ? (double)srv->completed / out->elapsed_s : 0.0;
     if (!srv->lat_us.empty()) {
@@ -414,6 +583,7 @@ int pir_serve_stats_get(pir_server* sv, pir_serve_stats* out, int reset) {
     if (reset) {
         srv->lat_us.clear();
         srv->submitted = srv->completed = srv->rejected = srv->batches = srv->h2d_bytes = 0;
+        srv->key_requests = srv->updates_applied = 0;
         for (auto& h : srv->hist) h = 0;
         srv->max_inflight = 0;
         srv->t0 = Clock::now();

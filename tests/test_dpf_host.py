@@ -52,3 +52,21 @@ def test_gen_rejects_bad_arguments():
     assert lib.pir_dpf_gen(0, 2, None, p, p, p) == _native.PIR_E_INVAL
     assert lib.pir_dpf_eval_async(None, None, 1, 1, 1, None, 4, None) == _native.PIR_E_INVAL
     assert lib.pir_dpf_dpxor_async(None, None, 1, None, None) == _native.PIR_E_INVAL
+
+
+def test_reconstruct_is_xor_and_may_alias():
+    a = synth.stream_bytes(synth.S_KEY + 50, 96)
+    b = synth.stream_bytes(synth.S_KEY + 51, 96)
+    assert np.array_equal(pir.reconstruct(a, b), a ^ b)
+    lib = pir.lib()
+    x, y = a.copy(), b.copy()
+    assert lib.pir_reconstruct(x.ctypes.data, y.ctypes.data, 96, x.ctypes.data) == _native.PIR_OK
+    assert np.array_equal(x, a ^ b)
+    assert lib.pir_reconstruct(None, y.ctypes.data, 96, x.ctypes.data) == _native.PIR_E_INVAL
+
+
+def test_gen_accepts_bytes_roots():
+    r0, r1 = _roots(synth.S_KEY + 60)
+    k0, k1 = pir.dpf_gen(5, 4, bytes(r0), bytearray(r1))
+    o0, o1 = oracle.dpf_gen(5, 4, r0, r1)
+    assert np.array_equal(k0, o0) and np.array_equal(k1, o1)
