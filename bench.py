@@ -142,16 +142,16 @@ def cpu_baseline(db_host, sel_rows, n, r, sample_queries):
             "db_gbs_scanned": sample_queries * n * r / dt / 1e9}
 
 
-# VALU operations per tree-node expansion of the DPF evaluation (AES-128 in
-# the one-T-table form: one v_perm per lookup address, three rotations and
-# two three-input XORs per MixColumns column, 11 ops per key-schedule round):
-#   full (both 128-bit children): 110 key schedule + 1 + 45 round 1 (the second
-#     block differs only in column 0) + 576 rounds 2-9 + 56 last round + 18
-#     correction words = 806
+# VALU operations per tree-node expansion of the DPF evaluation (AES-128 with
+# the T-tables Te0 and Te2: one v_perm per lookup address; per MixColumns
+# column one rotation and three XOR instructions; 11 ops per key-schedule round):
+#   full (both 128-bit children): 110 key schedule + 1 + 40 round 1 (the second
+#     block differs only in column 0) + 512 rounds 2-9 + 56 last round + 18
+#     correction words = 737
 #   leaf (bit 0 of both children, at the last level): 99 + 3 key schedule + 1 +
-#     45 + 504 rounds 2-8 + 18 round 9 (column 0) + 6 last round (byte 0) + 10 = 686
-DPF_OPS_FULL = 806
-DPF_OPS_LEAF = 686
+#     40 + 448 rounds 2-8 + 16 round 9 (column 0) + 6 last round (byte 0) + 10 = 623
+DPF_OPS_FULL = 737
+DPF_OPS_LEAF = 623
 
 
 def dpf_bench(ctx, db, db_host, n, r, args, torch, pir):

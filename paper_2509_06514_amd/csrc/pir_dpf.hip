@@ -20,14 +20,17 @@
 // chains launches with small E near the root (few nodes: latency) and E = 5
 // below (many nodes: throughput, little HBM traffic).
 //
-// AES on the VALU: the round function uses one T-table (the MixColumns
-// column of each S-box output; the other three are byte rotations of it and
-// the S-box itself is its byte 1).  The table is replicated once per lane of
-// a wave in LDS -- entry i of lane l at byte 256*i + 4*l -- so the lookups of
-// a wave never collide in a bank and each address is a single v_perm_b32 of
-// the state word and the lane offset.  (A second, pre-rotated table would
-// save two rotations per column, but at 128 KiB of LDS per workgroup it
-// halves the waves per CU and measured slower.)
+// AES on the VALU: T-tables Te0 (the MixColumns column of each S-box output)
+// and Te2 (Te0 rotated by 16 bits); Te1 and Te3 are rotations, and
+// Te1[b] ^ Te3[d] = rotr(Te0[b] ^ Te2[d], 24) costs one rotation per column.
+// The S-box itself is byte 1 of Te0.  LDS serves a wave's 32-bit reads in
+// two halves of 32 lanes, so 32 copies of each table keep every lookup of a
+// half-wave in its own bank: row i of the 64 KiB table holds Te0[i] for lanes
+// 0..31 (mod 32) and then Te2[i] for the same lanes, and a lookup address is
+// one v_perm_b32 of the state word and a per-lane offset register.  (One
+// 64-copy Te0 table plus three rotations per column measured 9 % slower; a
+// 128 KiB layout halves the waves per CU and measured slower still.)
+
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -145,7 +148,7 @@ namespace {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr uint32_t kTabBytes = 256 * 64 * 4;  // 64 KiB: one copy per lane
+constexpr uint32_t kTabBytes = 256 * 64 * 4;  // 64 KiB: 32 copies of Te0 and of Te2
 
 // AES round constants x^(i-1) in GF(2^8), i = 1..10.
 __host__ __device__ constexpr uint32_t rcon(int i) {
@@ -155,13 +158,18 @@ __host__ __device__ constexpr uint32_t rcon(int i) {
 }
 
 struct Lut {
-    const uint32_t* tab;  // LDS table
-    uint32_t lane4;       // 4 * lane
+    const uint32_t* tab;  // LDS table: row i = 32 copies of Te0[i], then 32 of Te2[i]
+    uint32_t lane4;       // 4 * (lane % 32)
+    uint32_t lane4b;      // 128 + 4 * (lane % 32)
 
-    // T-table entry for byte K of s: byte address (s.byte[K] << 8) | lane4.
     template <int K>
     __device__ __forceinline__ uint32_t t(uint32_t s) const {
         const uint32_t addr = __builtin_amdgcn_perm(s, lane4, 0x0c0c0400u + (K << 8));
+        return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(tab) + addr);
+    }
+    template <int K>
+    __device__ __forceinline__ uint32_t u(uint32_t s) const {
+        const uint32_t addr = __builtin_amdgcn_perm(s, lane4b, 0x0c0c0400u + (K << 8));
         return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(tab) + addr);
     }
 };
@@ -180,7 +188,7 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
 // One column of SubBytes + ShiftRows + MixColumns + AddRoundKey.
 __device__ __forceinline__ uint32_t mix_col(const Lut& L, uint32_t a, uint32_t b, uint32_t c, uint32_t d,
                                             uint32_t k) {
-    return xor3(xor3(L.t<0>(a), rotr(L.t<1>(b), 24), rotr(L.t<2>(c), 16)), rotr(L.t<3>(d), 8), k);
+    return xor3(L.t<0>(a), L.u<2>(c), k) ^ rotr(L.t<1>(b) ^ L.u<3>(d), 24);
 }
 
 // Last-round column (no MixColumns).
@@ -301,7 +309,8 @@ k_dpf_expand(const uint8_t* __restrict__ keys, uint32_t key_bytes, uint32_t n, u
     // lookup's LDS address is the v_perm_b32 result itself
     __shared__ uint32_t s_tab[kTabBytes / 4];
     for (uint32_t m = threadIdx.x; m < kTabBytes / 16; m += BS) {
-        const uint32_t v = c_te0[m >> 4];
+        const uint32_t v0 = c_te0[m >> 4];
+        const uint32_t v = (m & 8) ? rotr(v0, 16) : v0;  // second half of the row: Te2
         reinterpret_cast<u32x4*>(s_tab)[m] = u32x4{v, v, v, v};
     }
     __syncthreads();
@@ -310,7 +319,7 @@ k_dpf_expand(const uint8_t* __restrict__ keys, uint32_t key_bytes, uint32_t n, u
     const uint32_t q = blockIdx.y;
     const u32x4* kq = reinterpret_cast<const u32x4*>(keys + (uint64_t)q * key_bytes);
     const uint32_t n1 = n + 1;
-    const Lut L{s_tab, (threadIdx.x & 63u) * 4u};
+    const Lut L{s_tab, (threadIdx.x & 31u) * 4u, 128u + (threadIdx.x & 31u) * 4u};
 
     u32x4 cur = (a == 0) ? kq[0] : in[q * in_stride + i];  // eq. 2 at the root
     uint32_t word = (E == 0) ? (cur.x & 1u) : 0u;
