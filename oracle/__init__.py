@@ -17,6 +17,13 @@ two-server reconstruction identity, special cases and linearity.
 (tests/test_dpf_oracle.py): FIPS-197 and SP 800-38A known answers, the
 S-box values FIPS-197 prints, and the point-function identity
 Eval(k0, x) XOR Eval(k1, x) = [x = alpha] by brute force.
+
+``fp_oracle.c`` is the inner product over F_p (IM-PIR Sec. 2 states D in
+F_p^{N x L}; the implemented XOR form is p = 2 on bits):
+r[l] = (sum_j v[j] * D[j][l]) mod p.  Its pins (tests/test_fp_oracle.py):
+unit queries return the record, additive shares of a unit vector
+reconstruct the record, p = 2 on 0/1 elements equals the XOR oracle, brute
+force against an int64 matrix product, and linearity.
 """
 import ctypes
 import os
@@ -25,7 +32,8 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = [os.path.join(_HERE, "dpxor_oracle.c"), os.path.join(_HERE, "dpf_oracle.c")]
+_SRCS = [os.path.join(_HERE, "dpxor_oracle.c"), os.path.join(_HERE, "dpf_oracle.c"),
+         os.path.join(_HERE, "fp_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared"]
 _lib = None
@@ -62,6 +70,8 @@ def _load():
         lib.oracle_dpf_eval_full.argtypes = [p, i32, p]
         lib.oracle_dpf_gen.restype = None
         lib.oracle_dpf_gen.argtypes = [u64, i32, p, p, p, p]
+        lib.oracle_fp_inner.restype = i32
+        lib.oracle_fp_inner.argtypes = [p, u64, u32, p, u32, p]
         lib.oracle_dpxor.restype = None
         lib.oracle_dpxor.argtypes = [p, u64, u32, p, p]
         lib.oracle_dpxor_batch.restype = None
@@ -158,4 +168,17 @@ def dpf_eval_full(key, n):
     key = _u8(key)
     out = np.zeros(((1 << n) + 7) // 8, np.uint8)
     _load().oracle_dpf_eval_full(key.ctypes.data, n, out.ctypes.data)
+    return out
+
+
+def fp_inner(db, v, p):
+    """r[l] = (sum_j v[j] * db[j][l]) mod p for a (N, L) uint8 database and N query bytes."""
+    db = np.ascontiguousarray(db, dtype=np.uint8)
+    n, L = db.shape
+    v = np.ascontiguousarray(np.asarray(v, dtype=np.uint8).reshape(-1)[:n])
+    if v.size < n:
+        raise ValueError("query shorter than N")
+    out = np.zeros(L, np.uint8)
+    if _load().oracle_fp_inner(db.ctypes.data, n, L, v.ctypes.data, p, out.ctypes.data) != 0:
+        raise MemoryError("oracle_fp_inner")
     return out
