@@ -242,6 +242,67 @@ def dpf_cpu_baseline(key_full_domain):
                       f"read), {dt:.2f} s on 1 host thread"}
 
 
+FP_SHAPE = (1 << 24, 32, 127)  # records, elements per record, p
+
+
+def fp_bench(ctx, args, torch, pir):
+    """Inner products over F_p on the int8 matrix cores (HBM-bound scan)."""
+    import numpy as np
+    import synth
+
+    n, L, p = FP_SHAPE
+    q = args.fp_queries
+    D = (synth.stream_bytes(synth.S_DB + 9, n * L).reshape(n, L) % p).astype(np.uint8)
+    db = ctx.load_fp_db(D, p)
+    stride = db.min_v_stride
+    rows = (synth.stream_bytes(synth.S_SEL + 9, q * stride).reshape(q, stride) & 127).astype(np.uint8)
+    # rows 0 and 1: additive shares of the unit vector at index i
+    i = n // 3
+    e = np.zeros(stride, np.int64)
+    e[i] = 1
+    rows[1] = ((e - (rows[0] % p)) % p).astype(np.uint8)
+    rows[:, n:] = 0
+    d_v = torch.from_numpy(rows).to("cuda:0")
+    d_out = torch.empty((q, L), dtype=torch.uint8, device="cuda:0")
+    out = {"n_records": n, "record_elems": L, "p": p, "q": q}
+    for qq in (q, 1):
+        def step():
+            db.inner_async(d_v, qq, d_out)
+        for _ in range(3):
+            step()
+        torch.cuda.synchronize()
+        ctx.timing(True)
+        ctx.timing_read(reset=True)
+        wall, per = time_steps(step, args.steps, torch)
+        t = ctx.timing_read(reset=True)
+        ctx.timing(False)
+        s1 = t["fp_ms"] / max(1, t["fp_launches"])
+        alg = n * L + qq * stride + qq * L
+        ach = alg / (s1 / 1e3) / 1e9
+        rec = {"ms_per_pass": wall / args.steps * 1e3, "queries_per_s": qq * args.steps / wall,
+               "latency_ms": {"p50": percentile(per, 0.5), "p99": percentile(per, 0.99)},
+               "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": ach / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": alg,
+                            "avg_launch_ms": s1}}
+        if qq == q:
+            out.update(rec)
+            ans = d_out.cpu().numpy()
+            out["two_server_check"] = bool(np.array_equal((ans[0].astype(int) + ans[1]) % p, D[i]))
+        else:
+            out["single_query"] = rec
+        log(f"F_p q={qq}: stage1 {s1:.3f} ms, {ach:.0f} GB/s")
+    if args.cpu_sample > 0:
+        import oracle
+        t0 = time.perf_counter()
+        oracle.fp_inner(D, rows[0][:n], p)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 1.0 / dt, "unit": "queries/s", "cores": 1, "kind": "oracle",
+                               "sample": f"1 query over N={n} records of {L} elements (p={p}) on 1 host thread, "
+                                         f"{dt:.2f} s"}
+    db.free()
+    return out
+
+
 SERVE_DBS = [(1 << 23, 32), (1 << 24, 128), (1 << 22, 1024)]
 
 
@@ -344,6 +405,8 @@ def main():
     ap.add_argument("--dpf-keys", type=int, default=8,
                     help="DPF keys (pairs of parties) evaluated per call in the DPF section (0 = skip)")
     ap.add_argument("--dpf-steps", type=int, default=5)
+    ap.add_argument("--fp-queries", type=int, default=64,
+                    help="queries per pass in the F_p inner-product section (0 = skip)")
     ap.add_argument("--serve", action="store_true", help="run the serving sweep (three resident DBs) instead")
     ap.add_argument("--serve-rates", default="1000,2000,5000,10000,20000,50000")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
@@ -488,6 +551,9 @@ def main():
 
     if args.dpf_keys > 0:
         result["dpf"] = dpf_bench(ctx, db, db_host, n, r, args, torch, pir)
+
+    if args.fp_queries > 0:
+        result["fp"] = fp_bench(ctx, args, torch, pir)
 
     if args.cpu_sample > 0:
         log(f"cpu_baseline: oracle on {args.cpu_sample} queries ...")

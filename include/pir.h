@@ -36,6 +36,7 @@ extern "C" {
 typedef struct pir_ctx pir_ctx;
 typedef struct pir_db pir_db;
 typedef struct pir_server pir_server;
+typedef struct pir_fpdb pir_fpdb;
 
 typedef enum pir_status {
     PIR_OK = 0,
@@ -188,6 +189,8 @@ typedef struct pir_timing {
     double stage2_ms;
     uint64_t dpf_evals;       /* DPF evaluations (each a chain of expansion kernels) */
     double dpf_ms;            /* their summed durations, first launch to last */
+    uint64_t fp_launches;     /* F_p inner-product main kernels */
+    double fp_ms;
 } pir_timing;
 
 int pir_timing_enable(pir_ctx* ctx, int on);
@@ -355,6 +358,50 @@ int pir_dpf_dpxor_async(pir_db* db, const void* d_keys, uint32_t n_keys, void* d
  * input.  Errors: PIR_E_INVAL for NULL pointers.
  */
 int pir_reconstruct(const uint8_t* ans0, const uint8_t* ans1, uint64_t record_bytes, uint8_t* out);
+
+/* ---------------------------------------------------------------- F_p */
+
+/*
+ * The answer over a prime field (IM-PIR Sec. 2 states the database as D in
+ * F_p^{N x L} and the server's answer as the inner product of the query
+ * vector with it; the XOR scan above is the case p = 2 on bits):
+ *
+ *     r_q[l] = ( sum over j < N of v_q[j] * D[j][l] ) mod p,   l < L.
+ *
+ * Elements are bytes: a record is L elements (one byte each, < p), a query
+ * is N bytes, one per record.  2 <= p <= 127.  Query bytes must be below 128
+ * (they are the integers they hold; values in [p, 128) are allowed and act
+ * as their residues).  Answers are L bytes per query, each in [0, p).  Two
+ * servers holding v and e_i - v (mod p) return answers that add to D[i]
+ * (mod p).
+ */
+
+/* Copy N records of L elements (row-major, N*L bytes) into HBM.  Fails with
+ * PIR_E_INVAL if an element is >= p, N or L is 0, or p is outside [2, 127].
+ * The database must be freed before its context. */
+int pir_fp_db_load(pir_ctx* ctx, const void* elements, uint64_t n_records, uint32_t record_elems, uint32_t p,
+                   pir_fpdb** out);
+int pir_fp_db_free(pir_fpdb* db);
+
+/* Records [first, first + count) back in row-major order. */
+int pir_fp_db_read(pir_fpdb* db, uint64_t first, uint64_t count, void* out_elements);
+
+/* Smallest query row pitch for the device call: N rounded up to 64 (0 for
+ * NULL).  Bytes of a row past N are read and meet zero records. */
+uint64_t pir_fp_min_v_stride(const pir_fpdb* db);
+
+/*
+ * Q queries on device buffers, asynchronous on hip_stream.  d_v: q rows of
+ * v_stride bytes (a multiple of 16, >= pir_fp_min_v_stride), base 16-byte
+ * aligned; d_out: q * L bytes.  1 <= q <= PIR_MAX_BATCH.  Shares the
+ * per-stream workspace rules of pir_dpxor_batch_async.
+ */
+int pir_fp_inner_async(pir_fpdb* db, const void* d_v, uint64_t v_stride, uint32_t q, void* d_out,
+                       void* hip_stream);
+
+/* Q queries, host in and out, synchronous: v holds q rows v_stride >= N
+ * bytes apart, out receives q rows of L bytes. */
+int pir_fp_inner(pir_fpdb* db, const uint8_t* v, uint64_t v_stride, uint32_t q, uint8_t* out);
 
 /* ---------------------------------------------------------------- memory */
 

@@ -12,7 +12,7 @@ from . import _native
 from ._native import (PIR_MAX_BATCH, PIR_VARIANT_AUTO, PIR_VARIANT_MFMA_F4, PIR_VARIANT_MFMA_I8,
                       PIR_VARIANT_VALU, PirError, check, lib)
 
-__all__ = ["Context", "Database", "Server", "KernelCfg", "PirError", "lib", "sel_stride_for",
+__all__ = ["Context", "Database", "FpDatabase", "Server", "KernelCfg", "PirError", "lib", "sel_stride_for",
            "dpf_key_bytes", "dpf_domain_bits", "dpf_gen", "reconstruct",
            "PIR_MAX_BATCH", "PIR_VARIANT_AUTO", "PIR_VARIANT_VALU", "PIR_VARIANT_MFMA_I8",
            "PIR_VARIANT_MFMA_F4"]
@@ -134,7 +134,18 @@ class Context:
         check(lib().pir_timing_read(self._h, ctypes.byref(t), 1 if reset else 0), "pir_timing_read")
         return {"stage1_launches": t.stage1_launches, "stage1_ms": t.stage1_ms,
                 "stage2_launches": t.stage2_launches, "stage2_ms": t.stage2_ms,
-                "dpf_evals": t.dpf_evals, "dpf_ms": t.dpf_ms}
+                "dpf_evals": t.dpf_evals, "dpf_ms": t.dpf_ms,
+                "fp_launches": t.fp_launches, "fp_ms": t.fp_ms}
+
+    def load_fp_db(self, elements, p):
+        """Load an (N, L) uint8 database over F_p (every element < p, 2 <= p <= 127)."""
+        elements = _u8(elements)
+        if elements.ndim != 2:
+            raise ValueError("elements must be (N, L)")
+        n, L = elements.shape
+        h = ctypes.c_void_p()
+        check(lib().pir_fp_db_load(self._h, _ptr(elements), n, L, p, ctypes.byref(h)), "pir_fp_db_load")
+        return FpDatabase(self, h, n, L, p)
 
     def dpf_eval_async(self, d_keys, n, n_keys, n_leaves, d_sel, sel_stride=None, stream=None):
         """Full-domain DPF evaluation on the device (torch tensors), enqueued on `stream`.
@@ -266,6 +277,54 @@ class Database:
     def free(self):
         if self._h:
             check(lib().pir_db_free(self._h), "pir_db_free")
+            self._h = None
+
+
+class FpDatabase:
+    """A resident database over F_p (pir_fpdb): answers r_q = (v_q . D) mod p."""
+
+    def __init__(self, ctx, handle, n_records, record_elems, p):
+        self.ctx = ctx
+        self._h = handle
+        self.n_records, self.record_elems, self.p = n_records, record_elems, p
+        self.min_v_stride = lib().pir_fp_min_v_stride(handle)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def inner(self, v_rows):
+        """Q queries, host in/out: v_rows (Q, >= N) uint8 (< 128) -> (Q, L) answers."""
+        v_rows = _u8(v_rows)
+        if v_rows.ndim == 1:
+            v_rows = v_rows.reshape(1, -1)
+        q, stride = v_rows.shape
+        out = np.empty((q, self.record_elems), np.uint8)
+        check(lib().pir_fp_inner(self._h, _ptr(v_rows), stride, q, _ptr(out)), "pir_fp_inner")
+        return out
+
+    def inner_async(self, d_v, q, d_out, v_stride=None, stream=None):
+        """Q queries on device buffers (torch tensors) on `stream`; rows v_stride bytes apart."""
+        if v_stride is None:
+            v_stride = d_v.stride(0) * d_v.element_size() if d_v.dim() == 2 else self.min_v_stride
+        if d_v.device.type != "cuda" or d_out.device.type != "cuda":
+            raise ValueError("device tensors required")
+        if d_v.numel() * d_v.element_size() < (q - 1) * v_stride + self.min_v_stride:
+            raise ValueError("d_v too small")
+        if d_out.numel() * d_out.element_size() < q * self.record_elems:
+            raise ValueError("d_out too small")
+        check(lib().pir_fp_inner_async(self._h, ctypes.c_void_p(d_v.data_ptr()), v_stride, q,
+                                       ctypes.c_void_p(d_out.data_ptr()), _stream_handle(stream)),
+              "pir_fp_inner_async")
+
+    def read(self, first, count):
+        out = np.empty((count, self.record_elems), np.uint8)
+        check(lib().pir_fp_db_read(self._h, first, count, _ptr(out)), "pir_fp_db_read")
+        return out
+
+    def free(self):
+        if self._h:
+            check(lib().pir_fp_db_free(self._h), "pir_fp_db_free")
             self._h = None
 
 

@@ -45,7 +45,8 @@ class pir_kernel_cfg(ctypes.Structure):
 class pir_timing(ctypes.Structure):
     _fields_ = [("stage1_launches", ctypes.c_uint64), ("stage1_ms", ctypes.c_double),
                 ("stage2_launches", ctypes.c_uint64), ("stage2_ms", ctypes.c_double),
-                ("dpf_evals", ctypes.c_uint64), ("dpf_ms", ctypes.c_double)]
+                ("dpf_evals", ctypes.c_uint64), ("dpf_ms", ctypes.c_double),
+                ("fp_launches", ctypes.c_uint64), ("fp_ms", ctypes.c_double)]
 
 
 class pir_serve_config(ctypes.Structure):
@@ -106,6 +107,12 @@ SIGNATURES = {
     "pir_dpf_eval_async": (_I, [_P, _P, _U32, _U32, _U64, _P, _U64, _P]),
     "pir_dpf_dpxor_async": (_I, [_P, _P, _U32, _P, _P]),
     "pir_reconstruct": (_I, [_P, _P, _U64, _P]),
+    "pir_fp_db_load": (_I, [_P, _P, _U64, _U32, _U32, _PP]),
+    "pir_fp_db_free": (_I, [_P]),
+    "pir_fp_db_read": (_I, [_P, _U64, _U64, _P]),
+    "pir_fp_min_v_stride": (_U64, [_P]),
+    "pir_fp_inner_async": (_I, [_P, _P, _U64, _U32, _P, _P]),
+    "pir_fp_inner": (_I, [_P, _P, _U64, _U32, _P]),
     "pir_host_alloc": (_P, [ctypes.c_size_t]),
     "pir_host_free": (None, [_P]),
 }

@@ -14,7 +14,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpir.so")
 ARCH = "gfx950"
 
-SOURCES = ["pir_kernels.hip", "pir_dpf.hip", "pir_runtime.cpp", "pir_dpf_api.cpp", "pir_serve.cpp"]
+SOURCES = ["pir_kernels.hip", "pir_dpf.hip", "pir_fp.hip", "pir_runtime.cpp", "pir_dpf_api.cpp",
+           "pir_fp_api.cpp", "pir_serve.cpp"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}",

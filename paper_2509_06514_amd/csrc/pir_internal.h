@@ -90,4 +90,27 @@ void dpf_gen_host(uint64_t alpha, uint32_t n, const uint8_t root0[16], const uin
                   uint8_t* key1);
 void aes128_encrypt_host(const uint8_t key[16], const uint8_t in[16], uint8_t out[16]);
 
+// Inner products over F_p (pir_fp.hip).  Records in 64-record tiles,
+// column-major inside a tile; lpad = elements per record rounded up to 16.
+struct FpParams {
+    uint64_t tiles = 0;            // 64-record tiles holding records
+    uint64_t tiles_per_group = 0;  // <= kFpMaxTilesPerGroup (int32 sums stay exact)
+    uint64_t v_stride = 0;         // query row pitch (bytes)
+    uint32_t L = 0, lpad = 0, n_ct = 0;
+    uint32_t groups = 0, n_qt = 0, n_cg = 0;
+    uint32_t q_total = 0, p = 0, magic = 0;  // magic = floor(2^32 / p)
+};
+// A wave sums every 4th tile of its group: 2^31 / (64 * 127 * 126) > 2048
+// tiles per wave, so 8192 tiles per group keep every int32 sum exact.
+constexpr uint64_t kFpMaxTilesPerGroup = 8192;
+bool fp_supported(uint32_t rt, uint32_t ct, uint32_t kt);
+// rt row tiles (16 queries each), ct column tiles (16 elements each), kt tiles per wave step
+hipError_t launch_fp_stage1(const uint8_t* db, const uint8_t* v, uint8_t* partials, const FpParams& a, uint32_t rt,
+                            uint32_t ct, uint32_t kt, hipStream_t s);
+hipError_t launch_fp_stage2(const uint8_t* partials, uint32_t groups, uint64_t outputs, uint32_t p, uint32_t magic,
+                            uint8_t* out, hipStream_t s);
+hipError_t launch_fp_tile(const uint8_t* src, uint64_t nrec, uint32_t L, uint32_t lpad, uint8_t* dst, hipStream_t s);
+hipError_t launch_fp_untile(const uint8_t* src, uint64_t nrec, uint32_t L, uint32_t lpad, uint8_t* dst,
+                            hipStream_t s);
+
 }  // namespace pir

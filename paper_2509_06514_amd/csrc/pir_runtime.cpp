@@ -765,9 +765,12 @@ int pir_timing_read(pir_ctx* c, pir_timing* out, int reset) {
         } else if (t.stage == 2) {
             ctx->acc.stage2_launches++;
             ctx->acc.stage2_ms += ms;
-        } else {
+        } else if (t.stage == 3) {
             ctx->acc.dpf_evals++;
             ctx->acc.dpf_ms += ms;
+        } else {
+            ctx->acc.fp_launches++;
+            ctx->acc.fp_ms += ms;
         }
     }
     // e1 appears in two records (end of stage 1, start of stage 2): free each event once

@@ -93,7 +93,8 @@ struct Ctx {
     void release(Exec* e);
     hipEvent_t take_event();
     int plan_for(const Db& db, uint32_t q, const pir_kernel_cfg* cfg, Plan& p);
-    // records (a, b) as a timed interval of `stage` (1, 2: scan stages; 3: DPF evaluation)
+    // records (a, b) as a timed interval of `stage` (1, 2: scan stages; 3: DPF evaluation;
+    // 4: F_p main kernel)
     void add_timed(hipEvent_t a, hipEvent_t b, int stage);
     int enqueue_scan(const Db& db, const Plan& p, const uint32_t* d_sel, uint64_t stride_words, uint32_t q,
                      uint8_t* d_out, uint8_t* partials, hipStream_t s);
