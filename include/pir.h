@@ -336,7 +336,7 @@ int pir_dpf_gen(uint64_t alpha, uint32_t n, const uint8_t* root0, const uint8_t*
  * past that are not written.  1 <= n_leaves <= 2^n, n <= 40,
  * 1 <= n_keys <= PIR_MAX_BATCH.  The library keeps a scratch buffer per
  * stream for the tree levels (2 * ceil(n_leaves / 32) blocks per key in flight,
- * keys processed in groups of at most 1 GiB of scratch) and may synchronise
+ * keys processed in groups of at most 1.5 GiB of scratch) and may synchronise
  * the stream once to grow it.  Errors: PIR_E_INVAL, PIR_E_NOMEM, PIR_E_DEVICE.
  */
 int pir_dpf_eval_async(pir_ctx* ctx, const void* d_keys, uint32_t n, uint32_t n_keys, uint64_t n_leaves,

@@ -9,7 +9,7 @@ namespace pir {
 namespace {
 
 constexpr uint32_t kMaxDomainBits = 40;
-constexpr uint64_t kNodeScratchBudget = 1ull << 30;  // tree-level scratch per call
+constexpr uint64_t kNodeScratchBudget = 3ull << 29;  // tree-level scratch per call (1.5 GiB)
 constexpr uint64_t kSelScratchBudget = 2ull << 30;   // selection rows of the key-to-answer path
 
 uint64_t words_for(uint64_t n_leaves) { return (n_leaves + 31) / 32; }

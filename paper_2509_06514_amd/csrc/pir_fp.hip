@@ -166,20 +166,42 @@ k_fp_stage1(const uint8_t* __restrict__ db, const uint8_t* __restrict__ v, uint8
     }
 }
 
-// Stage 2: out[q][c] = (sum over groups of partials) mod p; 64 outputs per
-// workgroup, the groups split over its 4 waves.
+// Stage 2, in two levels so that no thread walks all groups (with few
+// outputs that walk is a long chain of dependent byte loads):
+//  1. block (x, y) sums groups [64 y, 64 y + 64) for 64 outputs -- 16 loads
+//     per thread, all independent -- into tmp[y][o];
+//  2. one thread per output adds the slices and reduces mod p.
+constexpr uint32_t kFpSliceGroups = 64;
+
 __global__ void __launch_bounds__(kFpThreads)
-k_fp_stage2(const uint8_t* __restrict__ partials, uint32_t groups, uint64_t outputs, uint32_t p, uint32_t magic,
-            uint8_t* __restrict__ out) {
+k_fp_reduce_slices(const uint8_t* __restrict__ partials, uint32_t groups, uint64_t outputs,
+                   uint32_t* __restrict__ tmp) {
     __shared__ uint32_t part[4][64];
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t o = (uint64_t)blockIdx.x * 64 + lane;
+    const uint32_t g0 = blockIdx.y * kFpSliceGroups;
     uint32_t s = 0;
-    if (o < outputs)
-        for (uint32_t g = w; g < groups; g += 4) s += partials[(uint64_t)g * outputs + o];
+    if (o < outputs) {
+#pragma unroll
+        for (uint32_t i = 0; i < kFpSliceGroups / 4; ++i) {
+            const uint32_t g = g0 + w + 4 * i;
+            if (g < groups) s += partials[(uint64_t)g * outputs + o];
+        }
+    }
     part[w][lane] = s;
     __syncthreads();
-    if (w == 0 && o < outputs) out[o] = (uint8_t)mod_p(part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane], p, magic);
+    if (w == 0 && o < outputs)
+        tmp[(uint64_t)blockIdx.y * outputs + o] = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+}
+
+__global__ void __launch_bounds__(kFpThreads)
+k_fp_finish(const uint32_t* __restrict__ tmp, uint32_t slices, uint64_t outputs, uint32_t p, uint32_t magic,
+            uint8_t* __restrict__ out) {
+    const uint64_t o = (uint64_t)blockIdx.x * kFpThreads + threadIdx.x;
+    if (o >= outputs) return;
+    uint32_t s = 0;  // < groups * 126 < 2^32
+    for (uint32_t k = 0; k < slices; ++k) s += tmp[(uint64_t)k * outputs + o];
+    out[o] = (uint8_t)mod_p(s, p, magic);
 }
 
 // Row-major records [0, nrec) of a chunk -> tiles at dst (the chunk starts
@@ -241,10 +263,19 @@ hipError_t launch_fp_stage1(const uint8_t* db, const uint8_t* v, uint8_t* partia
     return hipErrorInvalidValue;
 }
 
+size_t fp_stage2_tmp_bytes(uint32_t groups, uint64_t outputs) {
+    return (size_t)((groups + kFpSliceGroups - 1) / kFpSliceGroups) * outputs * 4;
+}
+
 hipError_t launch_fp_stage2(const uint8_t* partials, uint32_t groups, uint64_t outputs, uint32_t p, uint32_t magic,
-                            uint8_t* out, hipStream_t s) {
-    const uint32_t grid = (uint32_t)((outputs + 63) / 64);
-    hipLaunchKernelGGL(k_fp_stage2, dim3(grid), dim3(kFpThreads), 0, s, partials, groups, outputs, p, magic, out);
+                            uint32_t* tmp, uint8_t* out, hipStream_t s) {
+    const uint32_t slices = (groups + kFpSliceGroups - 1) / kFpSliceGroups;
+    hipLaunchKernelGGL(k_fp_reduce_slices, dim3((uint32_t)((outputs + 63) / 64), slices), dim3(kFpThreads), 0, s,
+                       partials, groups, outputs, tmp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fp_finish, dim3((uint32_t)((outputs + kFpThreads - 1) / kFpThreads)), dim3(kFpThreads), 0,
+                       s, tmp, slices, outputs, p, magic, out);
     return hipGetLastError();
 }
 

@@ -64,7 +64,8 @@ int enqueue_fp(FpDb& db, const uint8_t* d_v, uint64_t v_stride, uint32_t q, uint
     uint32_t rt, ct, kt;
     fp_plan(db, q, a, rt, ct, kt);
     a.v_stride = v_stride;
-    const size_t need = (size_t)a.groups * q * db.L;
+    const size_t part_bytes = ((size_t)a.groups * q * db.L + 255) / 256 * 256;
+    const size_t need = part_bytes + fp_stage2_tmp_bytes(a.groups, (uint64_t)q * db.L);
     if (need > ws.bytes) {
         if (ws.ptr && may_sync) {
             hipError_t e = hipStreamSynchronize(s);
@@ -85,7 +86,8 @@ int enqueue_fp(FpDb& db, const uint8_t* d_v, uint64_t v_stride, uint32_t q, uint
     hipError_t e = launch_fp_stage1((const uint8_t*)db.data.ptr, d_v, (uint8_t*)ws.ptr, a, rt, ct, kt, s);
     if (e != hipSuccess) return hip_fail(e, "F_p stage-1 launch");
     if (e1) (void)hipEventRecord(e1, s);
-    e = launch_fp_stage2((const uint8_t*)ws.ptr, a.groups, (uint64_t)q * db.L, db.p, db.magic, d_out, s);
+    e = launch_fp_stage2((const uint8_t*)ws.ptr, a.groups, (uint64_t)q * db.L, db.p, db.magic,
+                         (uint32_t*)((uint8_t*)ws.ptr + part_bytes), d_out, s);
     if (e != hipSuccess) return hip_fail(e, "F_p stage-2 launch");
     if (timed && e0 && e1) ctx->add_timed(e0, e1, 4);
     return PIR_OK;

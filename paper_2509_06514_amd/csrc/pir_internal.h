@@ -107,8 +107,10 @@ bool fp_supported(uint32_t rt, uint32_t ct, uint32_t kt);
 // rt row tiles (16 queries each), ct column tiles (16 elements each), kt tiles per wave step
 hipError_t launch_fp_stage1(const uint8_t* db, const uint8_t* v, uint8_t* partials, const FpParams& a, uint32_t rt,
                             uint32_t ct, uint32_t kt, hipStream_t s);
+// cross-group reduction: tmp holds fp_stage2_tmp_bytes(groups, outputs)
+size_t fp_stage2_tmp_bytes(uint32_t groups, uint64_t outputs);
 hipError_t launch_fp_stage2(const uint8_t* partials, uint32_t groups, uint64_t outputs, uint32_t p, uint32_t magic,
-                            uint8_t* out, hipStream_t s);
+                            uint32_t* tmp, uint8_t* out, hipStream_t s);
 hipError_t launch_fp_tile(const uint8_t* src, uint64_t nrec, uint32_t L, uint32_t lpad, uint8_t* dst, hipStream_t s);
 hipError_t launch_fp_untile(const uint8_t* src, uint64_t nrec, uint32_t L, uint32_t lpad, uint8_t* dst,
                             hipStream_t s);

@@ -688,6 +688,11 @@ int pir_tune(pir_db* d, uint32_t q, pir_kernel_cfg* out) {
         return fail(PIR_E_DEVICE, "event create");
     float best = 1e30f;
     pir_kernel_cfg best_cfg{};
+    struct Timed {
+        pir_kernel_cfg cfg;
+        float ms;
+    };
+    std::vector<Timed> timed;
     DevBuf ws;
     const bool was_timing = ctx->timing_on.exchange(false);
     const bool verbose = std::getenv("PIR_TUNE_VERBOSE") != nullptr;
@@ -720,10 +725,52 @@ int pir_tune(pir_db* d, uint32_t q, pir_kernel_cfg* out) {
         if (verbose)
             fprintf(stderr, "[pir_tune] q=%u variant=%u q_tile=%u unroll=%u groups=%u: %.4f ms\n", q, c.variant,
                     c.q_tile, c.unroll, p.groups, ms);
+        pir_kernel_cfg done = c;
+        done.groups = p.groups;
+        timed.push_back({done, ms});
         if (ms < best) {
             best = ms;
-            best_cfg = c;
-            best_cfg.groups = p.groups;
+            best_cfg = done;
+        }
+    }
+    // Final round: the candidates within 5 % of the best (at most 6) again,
+    // round-robin so that they share the device's clock and thermal state;
+    // the lowest median of 4 rounds of 4 launches wins.
+    std::sort(timed.begin(), timed.end(), [](const Timed& x, const Timed& y) { return x.ms < y.ms; });
+    std::vector<Timed> fin;
+    for (const Timed& t : timed)
+        if (t.ms <= 1.05f * best && fin.size() < 6) fin.push_back(t);
+    if (fin.size() > 1) {
+        std::vector<std::vector<float>> samples(fin.size());
+        for (int round = 0; round < 4; ++round)
+            for (size_t k = 0; k < fin.size(); ++k) {
+                Plan p;
+                p.variant = fin[k].cfg.variant;
+                p.qt = fin[k].cfg.q_tile;
+                p.unroll = fin[k].cfg.unroll;
+                p.groups = fin[k].cfg.groups;
+                if (finish_plan(g, q, p) || ws.ensure(partial_bytes(g, p, q)) != hipSuccess) continue;
+                (void)hipEventRecord(a, s);
+                for (int i = 0; i < 4; ++i)
+                    (void)ctx->enqueue_scan(*db, p, (const uint32_t*)sel.ptr, stride / 4, q, (uint8_t*)outb.ptr,
+                                            (uint8_t*)ws.ptr, s);
+                (void)hipEventRecord(b, s);
+                float ms = 0;
+                if (hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess)
+                    samples[k].push_back(ms / 4);
+            }
+        float best_med = 1e30f;
+        for (size_t k = 0; k < fin.size(); ++k) {
+            if (samples[k].empty()) continue;
+            std::sort(samples[k].begin(), samples[k].end());
+            const float med = samples[k][samples[k].size() / 2];
+            if (verbose)
+                fprintf(stderr, "[pir_tune] final q=%u variant=%u q_tile=%u unroll=%u groups=%u: %.4f ms\n", q,
+                        fin[k].cfg.variant, fin[k].cfg.q_tile, fin[k].cfg.unroll, fin[k].cfg.groups, med);
+            if (med < best_med) {
+                best_med = med;
+                best_cfg = fin[k].cfg;
+            }
         }
     }
     ctx->timing_on.store(was_timing);
