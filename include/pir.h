@@ -174,6 +174,19 @@ int pir_get_cfg(pir_db* db, uint32_t q, pir_kernel_cfg* out);
  */
 int pir_tune(pir_db* db, uint32_t q, pir_kernel_cfg* out);
 
+/*
+ * Graph replay (on by default): the scan's launches (stage 1 + stage 2) are
+ * captured once per (database buffer, plan, query count, device pointers)
+ * into a hipGraph on a private stream and replayed with one graph launch on
+ * the caller's stream; pir_dpxor, pir_dpxor_batch, the asynchronous calls,
+ * the key-to-answer path and the server all go through this cache (up to 256
+ * graphs per context, least recently used evicted; a database's graphs are
+ * dropped when it is freed).  While timing is enabled the launches are
+ * enqueued one by one instead, so that each stage can be timed.  on = 0
+ * turns replay off for this context.
+ */
+int pir_graphs_enable(pir_ctx* ctx, int on);
+
 /* ---------------------------------------------------------------- timing */
 
 /*

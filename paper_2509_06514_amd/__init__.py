@@ -126,6 +126,10 @@ class Context:
         check(lib().pir_db_load(self._h, _ptr(records), n, r, ctypes.byref(h)), "pir_db_load")
         return Database(self, h)
 
+    def graphs(self, on=True):
+        """Replay the scan's launches from captured hipGraphs (default) or enqueue them one by one."""
+        check(lib().pir_graphs_enable(self._h, 1 if on else 0), "pir_graphs_enable")
+
     def timing(self, on=True):
         check(lib().pir_timing_enable(self._h, 1 if on else 0), "pir_timing_enable")
 

@@ -90,6 +90,7 @@ SIGNATURES = {
     "pir_dpxor_batch_async_cfg": (_I, [_P, _P, _U64, _U32, _P, _P, ctypes.POINTER(pir_kernel_cfg)]),
     "pir_get_cfg": (_I, [_P, _U32, ctypes.POINTER(pir_kernel_cfg)]),
     "pir_tune": (_I, [_P, _U32, ctypes.POINTER(pir_kernel_cfg)]),
+    "pir_graphs_enable": (_I, [_P, _I]),
     "pir_timing_enable": (_I, [_P, _I]),
     "pir_timing_read": (_I, [_P, ctypes.POINTER(pir_timing), _I]),
     "pir_serve_create": (_I, [_P, ctypes.POINTER(pir_serve_config), _PP]),

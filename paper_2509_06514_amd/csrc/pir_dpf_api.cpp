@@ -174,7 +174,7 @@ int pir_dpf_dpxor_async(pir_db* d, const void* d_keys, uint32_t n_keys, void* d_
         if ((rc = eval_groups(ctx, (const uint8_t*)d_keys + (uint64_t)q0 * kb, n, q, g.n, (uint32_t*)sb->ptr,
                               stride / 4, s)))
             return rc;
-        if ((rc = ctx->enqueue_scan(*db, p, (const uint32_t*)sb->ptr, stride / 4, q,
+        if ((rc = ctx->launch_scan(*db, p, (const uint32_t*)sb->ptr, stride / 4, q,
                                     (uint8_t*)d_out + (uint64_t)q0 * g.R, (uint8_t*)pb->ptr, s)))
             return rc;
     }

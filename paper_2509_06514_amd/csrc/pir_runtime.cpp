@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <tuple>
 #include <fstream>
 #include <map>
 #include <memory>
@@ -148,6 +149,8 @@ size_t partial_bytes(const Geometry& g, const Plan& p, uint32_t q) {
 
 Ctx::~Ctx() {
     (void)hipSetDevice(device);
+    drop_graphs(nullptr);
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
     for (auto& e : pool) {
         if (e->stream) (void)hipStreamDestroy(e->stream);
     }
@@ -239,6 +242,91 @@ int Ctx::enqueue_scan(const Db& db, const Plan& p, const uint32_t* d_sel, uint64
         pending.push_back({e0, e1, 1});
         pending.push_back({e1, e2, 2});
     }
+    return PIR_OK;
+}
+
+bool GraphKey::operator<(const GraphKey& o) const {
+    return std::tie(data, n, R, variant, qt, unroll, groups, q, sel, stride_words, out, partials) <
+           std::tie(o.data, o.n, o.R, o.variant, o.qt, o.unroll, o.groups, o.q, o.sel, o.stride_words, o.out,
+                    o.partials);
+}
+
+constexpr size_t kMaxGraphs = 256;
+
+void Ctx::drop_graphs(const void* db) {
+    std::lock_guard<std::mutex> lk(graph_mu);
+    for (auto it = graphs.begin(); it != graphs.end();) {
+        if (db == nullptr || it->second.db == db) {
+            (void)hipGraphExecDestroy(it->second.exec);
+            (void)hipGraphDestroy(it->second.graph);
+            it = graphs.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+// The scan's two launches as one graph launch.  A graph is captured on the
+// context's private capture stream (nothing runs there) the first time a key
+// is seen, instantiated, and replayed on the caller's stream afterwards.  The
+// kernels write every byte they read back, so no memset node is needed.
+int Ctx::launch_scan(const Db& db, const Plan& p, const uint32_t* d_sel, uint64_t stride_words, uint32_t q,
+                     uint8_t* d_out, uint8_t* partials, hipStream_t s) {
+    if (timing_on.load() || !graphs_on.load() || !capture_stream)
+        return enqueue_scan(db, p, d_sel, stride_words, q, d_out, partials, s);
+    const GraphKey key{db.data.ptr, db.geo.n, db.geo.R, p.variant, p.qt, p.unroll, p.groups, q,
+                       d_sel,       stride_words, d_out, partials};
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(graph_mu);
+        auto it = graphs.find(key);
+        if (it != graphs.end()) {
+            it->second.last_use = ++graph_clock;
+            exec = it->second.exec;
+        }
+    }
+    if (!exec) {
+        GraphEntry ent;
+        ent.db = &db;
+        {
+            std::lock_guard<std::mutex> cl(capture_mu);
+            hipError_t e = hipStreamBeginCapture(capture_stream, hipStreamCaptureModeRelaxed);
+            if (e != hipSuccess) return hip_fail(e, "graph capture");
+            const bool was_timing = timing_on.exchange(false);
+            const int rc = enqueue_scan(db, p, d_sel, stride_words, q, d_out, partials, capture_stream);
+            if (was_timing) timing_on.store(true);
+            e = hipStreamEndCapture(capture_stream, &ent.graph);
+            if (rc != PIR_OK || e != hipSuccess) {
+                if (ent.graph) (void)hipGraphDestroy(ent.graph);
+                return rc != PIR_OK ? rc : hip_fail(e, "graph capture");
+            }
+            e = hipGraphInstantiate(&ent.exec, ent.graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(ent.graph);
+                return hip_fail(e, "graph instantiate");
+            }
+        }
+        std::lock_guard<std::mutex> lk(graph_mu);
+        if (graphs.size() >= kMaxGraphs) {
+            // evict the least recently used graph; it may still be running
+            auto lru = graphs.begin();
+            for (auto it = graphs.begin(); it != graphs.end(); ++it)
+                if (it->second.last_use < lru->second.last_use) lru = it;
+            (void)hipDeviceSynchronize();
+            (void)hipGraphExecDestroy(lru->second.exec);
+            (void)hipGraphDestroy(lru->second.graph);
+            graphs.erase(lru);
+        }
+        ent.last_use = ++graph_clock;
+        auto ins = graphs.emplace(key, ent);
+        if (!ins.second) {  // another thread captured the same key meanwhile
+            (void)hipGraphExecDestroy(ent.exec);
+            (void)hipGraphDestroy(ent.graph);
+        }
+        exec = ins.first->second.exec;
+    }
+    hipError_t e = hipGraphLaunch(exec, s);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
     return PIR_OK;
 }
 
@@ -344,6 +432,8 @@ int pir_ctx_create(int hip_device, pir_ctx** out) {
     ctx->n_cu = prop.multiProcessorCount;
     int rc = ctx->bind();
     if (rc) return rc;
+    e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
     ctx->load_tune_cache();
     *out = reinterpret_cast<pir_ctx*>(ctx.release());
     return PIR_OK;
@@ -491,6 +581,7 @@ int pir_db_free(pir_db* d) {
     Db* db = reinterpret_cast<Db*>(d);
     (void)db->ctx->bind();
     (void)hipDeviceSynchronize();
+    db->ctx->drop_graphs(db);
     db->data.reset();
     if (db->ctx_stream) (void)hipStreamDestroy(db->ctx_stream);
     delete db;
@@ -553,7 +644,7 @@ int pir_dpxor_batch_async_cfg(pir_db* d, const void* d_sel, uint64_t sel_stride,
         }
         partials = (uint8_t*)ws.ptr;
     }
-    return ctx->enqueue_scan(*db, p, (const uint32_t*)d_sel, sel_stride / 4, q, (uint8_t*)d_out, partials, s);
+    return ctx->launch_scan(*db, p, (const uint32_t*)d_sel, sel_stride / 4, q, (uint8_t*)d_out, partials, s);
 }
 
 int pir_dpxor_batch_async(pir_db* d, const void* d_sel, uint64_t sel_stride, uint32_t q, void* d_out,
@@ -602,7 +693,7 @@ int pir_dpxor_batch(pir_db* d, const uint8_t* sel_bits, uint64_t sel_stride, uin
     }
     if ((e = hipMemcpyAsync(ex->d_sel.ptr, hs, sel_bytes, hipMemcpyHostToDevice, ex->stream)) != hipSuccess)
         return hip_fail(e, "selection upload");
-    rc = ctx->enqueue_scan(*db, p, (const uint32_t*)ex->d_sel.ptr, dstride / 4, q, (uint8_t*)ex->d_out.ptr,
+    rc = ctx->launch_scan(*db, p, (const uint32_t*)ex->d_sel.ptr, dstride / 4, q, (uint8_t*)ex->d_out.ptr,
                            (uint8_t*)ex->partials.ptr, ex->stream);
     if (rc) return rc;
     if ((e = hipMemcpyAsync(ex->h_out.ptr, ex->d_out.ptr, out_bytes, hipMemcpyDeviceToHost, ex->stream)) !=
@@ -784,6 +875,13 @@ int pir_tune(pir_db* d, uint32_t q, pir_kernel_cfg* out) {
         ctx->save_tune_cache();
     }
     if (out) *out = best_cfg;
+    return PIR_OK;
+}
+
+int pir_graphs_enable(pir_ctx* c, int on) {
+    clear_error();
+    if (!c) return fail(PIR_E_INVAL, "NULL context");
+    reinterpret_cast<Ctx*>(c)->graphs_on.store(on != 0);
     return PIR_OK;
 }
 

@@ -73,6 +73,25 @@ struct DpfWs {
     DevBuf nodes, sel;
 };
 
+// A captured scan (stage 1 + stage 2) for one database buffer, plan, query
+// count and set of device pointers, instantiated once and replayed.
+struct GraphKey {
+    const void* data;
+    uint64_t n;
+    uint32_t R, variant, qt, unroll, groups, q;
+    const void* sel;
+    uint64_t stride_words;
+    const void* out;
+    const void* partials;
+    bool operator<(const GraphKey& o) const;
+};
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void* db = nullptr;
+    uint64_t last_use = 0;
+};
+
 struct Ctx {
     int device = 0;
     std::string arch;
@@ -83,6 +102,12 @@ struct Ctx {
     std::unordered_map<hipStream_t, DpfWs> dpf_ws;       // per caller stream
     std::map<std::string, pir_kernel_cfg> tuned;
     std::atomic<bool> timing_on{false};
+    std::atomic<bool> graphs_on{true};
+    std::mutex graph_mu;                  // guards `graphs`
+    std::mutex capture_mu;                // one capture at a time on capture_stream
+    hipStream_t capture_stream = nullptr;
+    std::map<GraphKey, GraphEntry> graphs;
+    uint64_t graph_clock = 0;
     std::vector<TimedPair> pending;
     std::vector<hipEvent_t> free_events;
     pir_timing acc{};
@@ -98,6 +123,10 @@ struct Ctx {
     void add_timed(hipEvent_t a, hipEvent_t b, int stage);
     int enqueue_scan(const Db& db, const Plan& p, const uint32_t* d_sel, uint64_t stride_words, uint32_t q,
                      uint8_t* d_out, uint8_t* partials, hipStream_t s);
+    // enqueue_scan through the graph cache (eager while timing is on or graphs are off)
+    int launch_scan(const Db& db, const Plan& p, const uint32_t* d_sel, uint64_t stride_words, uint32_t q,
+                    uint8_t* d_out, uint8_t* partials, hipStream_t s);
+    void drop_graphs(const void* db);  // all graphs of a database (nullptr: every graph)
     std::string tune_key(const Geometry& g, uint32_t q) const;
     void save_tune_cache();
     void load_tune_cache();

@@ -251,7 +251,7 @@ bool Server::dispatch_one(Slot& s) {
                                d.dstride / 4, s.stream);
     }
     if (rc == PIR_OK)
-        rc = ctx->enqueue_scan(*d.db, p, (const uint32_t*)s.d_sel.ptr, d.dstride / 4, n, (uint8_t*)s.d_out.ptr,
+        rc = ctx->launch_scan(*d.db, p, (const uint32_t*)s.d_sel.ptr, d.dstride / 4, n, (uint8_t*)s.d_out.ptr,
                                (uint8_t*)s.partials.ptr, s.stream);
     if (rc == PIR_OK) {
         e = hipMemcpyAsync(s.h_out.ptr, s.d_out.ptr, (size_t)g.R * n, hipMemcpyDeviceToHost, s.stream);
