@@ -127,19 +127,31 @@ def roofline_for(variant, n, r, q, stage1_ms_avg, traffic):
             "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": stage1_ms_avg}
 
 
-def cpu_baseline(db_host, sel_rows, n, r, sample_queries):
-    """The oracle, single-threaded, on `sample_queries` full queries of the same workload."""
+def cpu_baseline(db_host, sel_rows, n, r, sample_queries, threads):
+    """The oracle on the host: `sample_queries` full queries on one thread, then one
+    query per thread on `threads` threads at once (the CPU-PIR arrangement of one
+    query per core).  The C oracle releases the interpreter lock while it runs."""
+    import threading
+
     import oracle
 
     t0 = time.perf_counter()
     for i in range(sample_queries):
         oracle.dpxor(db_host, sel_rows[i])
-    dt = time.perf_counter() - t0
-    qps = sample_queries / dt
-    return {"value": qps, "unit": "queries/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sample_queries} full queries (N={n}, R={r}) on 1 host thread, "
-                      f"{dt:.1f} s; DB GB/s scanned {sample_queries * n * r / dt / 1e9:.2f}",
-            "db_gbs_scanned": sample_queries * n * r / dt / 1e9}
+    dt1 = time.perf_counter() - t0
+    ths = [threading.Thread(target=oracle.dpxor, args=(db_host, sel_rows[i % len(sel_rows)]))
+           for i in range(threads)]
+    t0 = time.perf_counter()
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    dtn = time.perf_counter() - t0
+    return {"value": threads / dtn, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"{threads} full queries (N={n}, R={r}), one per host thread, {dtn:.1f} s; "
+                      f"single thread: {sample_queries} queries in {dt1:.1f} s",
+            "single_thread": {"value": sample_queries / dt1, "unit": "queries/s", "cores": 1,
+                              "db_gbs_scanned": sample_queries * n * r / dt1 / 1e9}}
 
 
 # VALU operations per tree-node expansion of the DPF evaluation (AES-128 with
@@ -309,7 +321,8 @@ SERVE_DBS = [(1 << 23, 32), (1 << 24, 128), (1 << 22, 1024)]
 def serve_bench(args):
     """Open-loop Poisson arrivals over three resident databases (continuous batching).
 
-    Each rate runs for args.serve_seconds; each request goes to a database
+    Each rate runs for at least 10 s or 20k requests (and at least
+    args.serve_seconds); each request goes to a database
     drawn uniformly; selections come from a pre-generated pool per database
     (contents do not change the scan's cost).  Latency is submit -> answer in
     host memory, measured by the server.
@@ -329,8 +342,21 @@ def serve_bench(args):
         hosts.append(h)
         log(f"serve: loaded DB{k} N={n} R={r}")
     pool = [synth.selections(n, 16, seed=synth.S_SEL + 50 + k) for k, (n, r) in enumerate(SERVE_DBS)]
+    if args.serve_keys:
+        # requests are DPF keys: a pool per database (the server's cost does not
+        # depend on alpha), plus one key pair per database checked afterwards
+        kpool, checks = [], []
+        for k, (n, r) in enumerate(SERVE_DBS):
+            nb = pir.dpf_domain_bits(n)
+            keys = []
+            for j in range(16):
+                root = synth.stream_bytes(synth.S_KEY + 100 * k + j, 32)
+                keys.append(pir.dpf_gen((j * 7919) % n, nb, root[:16], root[16:])[j % 2])
+            kpool.append(keys)
+            root = synth.stream_bytes(synth.S_KEY + 100 * k + 99, 32)
+            checks.append((n // 2,) + pir.dpf_gen(n // 2, nb, root[:16], root[16:]))
     results = []
-    rates = [int(x) for x in args.serve_rates.split(",")]
+    rates = [int(x) for x in (args.serve_key_rates if args.serve_keys else args.serve_rates).split(",")]
     threads_n = args.serve_threads
     for rate in rates:
         srv = pir.Server(ctx, q_max=args.serve_qmax, max_wait_us=args.serve_wait_us, n_slots=args.serve_slots,
@@ -340,7 +366,9 @@ def serve_bench(args):
         for d in dbs:
             d.tune(args.serve_qmax)
         outs = [np.zeros((4096, r), np.uint8) for (n, r) in SERVE_DBS]
-        stop_at = time.perf_counter() + args.serve_seconds
+        # at least 10 s or 20k requests per rate (whichever comes first), at least serve_seconds
+        dur = min(10.0, max(args.serve_seconds, 20000.0 / rate))
+        stop_at = time.perf_counter() + dur
         pending = [[] for _ in range(threads_n)]
         rejected = [0] * threads_n
 
@@ -348,7 +376,7 @@ def serve_bench(args):
             rng = np.random.default_rng(1000 * rate + tid)
             t = time.perf_counter()
             k = 0
-            lib_submit = srv.submit_raw
+            lib_submit = srv.submit_key_raw if args.serve_keys else srv.submit_raw
             while True:
                 t += rng.exponential(threads_n / rate)
                 now = time.perf_counter()
@@ -359,9 +387,9 @@ def serve_bench(args):
                     while time.perf_counter() < t:
                         pass
                 w = int(rng.integers(0, 3))
-                sel = pool[w][k % 16]
+                src = kpool[w][k % 16] if args.serve_keys else pool[w][k % 16]
                 out = outs[w][(tid * 512 + k) % 4096]
-                rc, tk = lib_submit(ids[w], sel.ctypes.data, out.ctypes.data)
+                rc, tk = lib_submit(ids[w], src.ctypes.data, out.ctypes.data)
                 if rc == 0:
                     pending[tid].append(tk)
                 else:
@@ -378,13 +406,24 @@ def serve_bench(args):
             for tk in lst:
                 srv.wait(tk, 60000)
         st = srv.stats()
+        check = None
+        if args.serve_keys:
+            # the two parties' answers for one index per database reconstruct the record
+            check = True
+            for w, (alpha, k0, k1) in enumerate(checks):
+                a0, a1 = np.zeros(SERVE_DBS[w][1], np.uint8), np.zeros(SERVE_DBS[w][1], np.uint8)
+                t0k, t1k = srv.submit_key(ids[w], k0, a0), srv.submit_key(ids[w], k1, a1)
+                check &= srv.wait(t0k, 60000) == 0 and srv.wait(t1k, 60000) == 0
+                check &= bool(np.array_equal(a0 ^ a1, hosts[w][alpha]))
         srv.close()
         hist = {f"{1 << i}-{(2 << i) - 1}": c for i, c in enumerate(st["batch_hist"]) if c}
-        rec = {"offered_qps": rate, "achieved_qps": st["completed"] / args.serve_seconds,
+        rec = {"offered_qps": rate, "seconds": dur, "achieved_qps": st["completed"] / dur,
                "completed": st["completed"], "rejected": st["rejected"] + sum(rejected),
                "p50_ms": st["p50_us"] / 1e3, "p99_ms": st["p99_us"] / 1e3, "mean_ms": st["mean_us"] / 1e3,
                "batches": st["batches"], "batch_hist": hist, "max_inflight": st["max_inflight"],
-               "h2d_GBps": st["h2d_bytes"] / args.serve_seconds / 1e9}
+               "h2d_GBps": st["h2d_bytes"] / dur / 1e9}
+        if check is not None:
+            rec["two_server_check"] = bool(check)
         log(f"serve rate {rate}: {json.dumps(rec)}")
         results.append(rec)
     for d in dbs:
@@ -401,6 +440,13 @@ def main():
     ap.add_argument("--config", default="c4", choices=sorted(CONFIGS))
     ap.add_argument("--no-tune", action="store_true", help="use the default kernel plan")
     ap.add_argument("--cpu-sample", type=int, default=2, help="oracle queries for cpu_baseline (0 = skip)")
+    ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1),
+                    help="host threads for the all-core oracle baseline (one query each)")
+    ap.add_argument("--sel-fill", default="random", choices=["random", "zeros", "ones"],
+                    help="selection contents (zeros/ones: the scan must read the same bytes)")
+    ap.add_argument("--serve-keys", action="store_true", help="serving sweep with DPF keys as requests")
+    ap.add_argument("--serve-key-rates", default="500,1000,2000,4000",
+                    help="offered rates for --serve-keys (each key costs a full-domain evaluation)")
     ap.add_argument("--no-single", action="store_true", help="skip the single-query pass")
     ap.add_argument("--dpf-keys", type=int, default=8,
                     help="DPF keys (pairs of parties) evaluated per call in the DPF section (0 = skip)")
@@ -431,11 +477,13 @@ def main():
 
     if args.serve:
         res = serve_bench(args)
-        print(json.dumps({"metric": "serving p50/p99 latency vs offered load (3 resident DBs)",
+        print(json.dumps({"metric": "serving p50/p99 latency vs offered load (3 resident DBs"
+                                    + (", requests as DPF keys)" if args.serve_keys else ")"),
                           "unit": "ms", "data": "synthetic",
                           "config": {"dbs": [{"n_records": n, "record_bytes": r} for n, r in SERVE_DBS],
                                      "q_max": args.serve_qmax, "slots": args.serve_slots,
-                                     "max_wait_us": args.serve_wait_us, "seconds_per_rate": args.serve_seconds},
+                                     "max_wait_us": args.serve_wait_us,
+                                     "seconds_per_rate": "max(serve_seconds, min(10, 20000 / rate))"},
                           "rates": res}), flush=True)
         return
 
@@ -458,6 +506,8 @@ def main():
     log(f"generated {n * r / 2**30:.2f} GiB database in {time.perf_counter() - t:.1f}s")
     stride = pir.sel_stride_for(n)
     sel_host = synth.selections(n, q, seed=synth.S_SEL + 3, stride=stride)
+    if args.sel_fill != "random":
+        sel_host[:] = 0 if args.sel_fill == "zeros" else 0xFF
 
     ctx = pir.Context(0)
     t = time.perf_counter()
@@ -563,7 +613,7 @@ def main():
 
     if args.cpu_sample > 0:
         log(f"cpu_baseline: oracle on {args.cpu_sample} queries ...")
-        result["cpu_baseline"] = cpu_baseline(db_host, sel_host, n, r, args.cpu_sample)
+        result["cpu_baseline"] = cpu_baseline(db_host, sel_host, n, r, args.cpu_sample, args.cpu_threads)
     else:
         result["cpu_baseline"] = None
 

@@ -375,6 +375,12 @@ class Server:
               "pir_serve_update")
         return t.value
 
+    def submit_key_raw(self, db_id, key_ptr, out_ptr):
+        t = ctypes.c_uint64()
+        rc = lib().pir_serve_submit_key(self._h, db_id, ctypes.c_void_p(key_ptr), ctypes.c_void_p(out_ptr),
+                                        ctypes.byref(t))
+        return rc, t.value
+
     def submit_raw(self, db_id, sel_ptr, out_ptr):
         t = ctypes.c_uint64()
         rc = lib().pir_serve_submit(self._h, db_id, ctypes.c_void_p(sel_ptr), ctypes.c_void_p(out_ptr),
