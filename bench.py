@@ -58,6 +58,8 @@ def kernel_name(cfg, r):
         return f"k_stage1_mfma_lds<{mt}, {f4}, {cfg.unroll}, false>"
     if cfg.unroll == 7:  # 3-stage ring, selection operand spread once per workgroup
         return f"k_stage1_mfma_lds<{mt}, {f4}, 3, true>"
+    if 12 <= cfg.unroll <= 14:  # split K on a ring of 2/3/4 stages
+        return f"k_stage1_mfma_ks<{cfg.unroll - 10}>"
     return f"k_stage1_mfma<{mt}, {f4}>"
 
 

@@ -152,8 +152,9 @@ typedef struct pir_kernel_cfg {
     uint32_t q_tile;  /* queries per workgroup tile (variant-specific; 0 = default) */
     uint32_t unroll;  /* VALU: blocks per wave iteration; MFMA: 1 = register pipeline,
                          2/3/4/6 = LDS ring of that many stages, 7 = 3-stage ring with the
-                         selection operand spread once per workgroup (fp4, q_tile 64);
-                         0 = default */
+                         selection operand spread once per workgroup (fp4, q_tile 64),
+                         12/13/14 = split-K kernel on a ring of 2/3/4 stages (fp4,
+                         q_tile 64); 0 = default */
     uint32_t groups;  /* record groups = partial results per query (0 = default) */
 } pir_kernel_cfg;
 

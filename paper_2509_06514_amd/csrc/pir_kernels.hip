@@ -769,6 +769,228 @@ k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
         }
 }
 
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// A wave-uniform pointer re-read through v_readfirstlane.  The loads below
+// add a 32-bit lane offset to it; without this the compiler folds base and
+// offset into one 64-bit pointer per lane and load, kept in vector registers
+// and advanced with vector adds every step (12 of them per step instead of
+// the 8 that forming each address from the scalar base takes).
+__device__ __forceinline__ const uint8_t* uniform_ptr(const uint8_t* p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<const uint8_t*>(((uint64_t)hi << 32) | lo);
+}
+
+// Operand reads of one K-step for the split-K kernel: two sub-steps of two
+// database chunks (columns +0 and +64 words) at `b` and `b` + 1 KiB, and the
+// two selection words of each of the four row tiles at `a` + rt KiB.
+__device__ __forceinline__ void lds_read_ks(uint32_t b, uint32_t a, u32x4 (&bw)[4], u32x2 (&aw)[4]) {
+    asm volatile(
+        "ds_read_b128 %0, %8\n\t"
+        "ds_read_b128 %1, %8 offset:256\n\t"
+        "ds_read_b128 %2, %8 offset:1024\n\t"
+        "ds_read_b128 %3, %8 offset:1280\n\t"
+        "ds_read_b64 %4, %9\n\t"
+        "ds_read_b64 %5, %9 offset:1024\n\t"
+        "ds_read_b64 %6, %9 offset:2048\n\t"
+        "ds_read_b64 %7, %9 offset:3072\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(bw[0]), "=&v"(bw[1]), "=&v"(bw[2]), "=&v"(bw[3]), "=&v"(aw[0]), "=&v"(aw[1]),
+          "=&v"(aw[2]), "=&v"(aw[3])
+        : "v"(b), "v"(a));
+}
+
+// Split-K matrix-core scan (fp4, 64-query tiles).  The spread of an operand
+// word costs vector-ALU issue slots that the matrix cores then lose, and a
+// wave spreads (row tiles + column tiles) words per sub-step for
+// (row tiles x column tiles) MFMAs.  Here a wave owns 128 bit columns
+// (8 column tiles) instead of 64 and half of each K-step's blocks: wave w
+// takes column half c = w & 1 and sub-steps 2h, 2h+1 with h = w >> 1.  Per
+// K-step a wave spreads 2 x (8 + 4) words for 64 MFMAs instead of
+// 4 x (4 + 4).  The two K halves of a column are combined at the end: the
+// parity of a sum of counts is the XOR of their parities.
+//
+// Loads and the LDS ring are those of k_stage1_mfma_lds.  Each load's
+// address is a wave-uniform base plus a fixed 32-bit lane offset; the
+// selection offsets span three rows, which bounds the selection pitch
+// (checked by the launcher).
+template <int S>
+__global__ void __launch_bounds__(kThreads)
+k_stage1_mfma_ks(const uint32_t* __restrict__ db, const uint32_t* __restrict__ sel,
+                 uint8_t* __restrict__ partials, Stage1Params p) {
+    constexpr int MT = 4, NT = 8, QT = 64;
+    constexpr int kLoadsPerStep = 4 + MT;
+    constexpr uint32_t kStageSelBytes = QT * 16 * 4;
+    static_assert(S >= 2 && S <= 8, "ring stages");
+    extern __shared__ __attribute__((aligned(16))) uint8_t pir_ring[];
+    uint8_t* const ring_db = pir_ring;
+    uint8_t* const ring_sel = pir_ring + S * kStageDbBytes;
+
+    uint32_t group, ct, qt;
+    if (!decode_block(p.groups, p.n_ct, p.n_qt, group, ct, qt)) return;
+
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t c = wave & 1, h = wave >> 1;
+    const uint32_t j = lane & 15, g = lane >> 4;
+    const uint32_t q0 = qt * QT;
+    const uint64_t block_words = 8ull * p.R;
+
+    // loader geometry as in k_stage1_mfma_lds: wave w loads blocks w, w+4,
+    // w+8, w+12 of a step (lane l: words 4l..4l+3) and selection rows
+    // 4*(w + 4i) + l/16, word l%16.  A row past q_total reads the first row
+    // of its group of four (or row q0), a valid row never written out.
+    const uint8_t* db_tile = reinterpret_cast<const uint8_t*>(db + ct * 256);
+    const uint32_t db_off = 16 * lane;
+    const uint8_t* sel_base[MT];
+    uint32_t sel_off[MT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+        uint32_t r0 = q0 + 4 * (wave + 4 * i);
+        const bool any = r0 < p.q_total;
+        if (!any) r0 = q0;
+        const uint32_t rl = (any && r0 + lane / 16 < p.q_total) ? lane / 16 : 0;
+        sel_base[i] = reinterpret_cast<const uint8_t*>(sel + (uint64_t)r0 * p.stride_words);
+        sel_off[i] = rl * (uint32_t)(p.stride_words * 4) + 4 * (lane & 15);
+    }
+    auto issue = [&](uint64_t kb, uint32_t slot) {
+        uint8_t* dst_db = ring_db + slot * kStageDbBytes;
+        uint8_t* dst_sel = ring_sel + slot * kStageSelBytes;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t b = 4 * i + wave;
+            const uint8_t* base = uniform_ptr(db_tile + (kb + b) * block_words * 4);
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint32_t*>(base + db_off),
+                                             dst_db + b * 1024, 16, 0, 2);
+        }
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+            __builtin_amdgcn_global_load_lds(
+                reinterpret_cast<const uint32_t*>(uniform_ptr(sel_base[i] + kb * 4) + sel_off[i]),
+                dst_sel + (wave + 4 * i) * 256, 4, 0, 0);
+    };
+
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int rt = 0; rt < MT; ++rt)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[rt][t] = f32x4{0, 0, 0, 0};
+
+    // bw[2*sl + half]: sub-step 2h + sl, columns 128c + 64*half + 4j .. +3;
+    // aw[rt][sl]: selection word of row 16rt + j for that sub-step
+    auto mma = [&](const u32x4 bw[4], const u32x2 aw[MT]) {
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+            i32x8 bx[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) bx[t] = spread_fp4_b(bw[2 * sl + (t >> 2)][t & 3]);
+#pragma unroll
+            for (int rt = 0; rt < MT; ++rt) {
+                const i32x8 ax = spread_fp4_a(aw[rt][sl]);
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[rt][t] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(ax, bx[t], acc[rt][t], 4, 4, 0,
+                                                                                 127, 0, 127);
+            }
+        }
+    };
+    const uint32_t rd_db =
+        (uint32_t)(uintptr_t)(ring_db + (4 * g + 2 * h) * 1024 + (128 * c + 4 * j) * 4);
+    const uint32_t rd_sel = (uint32_t)(uintptr_t)(ring_sel + j * 64 + (4 * g + 2 * h) * 4);
+    auto compute_slot = [&](uint32_t slot) {
+        u32x4 bw[4];
+        u32x2 aw[MT];
+        lds_read_ks(rd_db + slot * kStageDbBytes, rd_sel + slot * kStageSelBytes, bw, aw);
+        mma(bw, aw);
+    };
+    const uint64_t b_begin = (uint64_t)group * p.units_per_group;
+    const uint64_t b_end = (b_begin + p.units_per_group < p.n_units) ? b_begin + p.units_per_group : p.n_units;
+    const uint64_t nsteps = (b_end - b_begin) / kMfmaBlocksPerStep;
+
+#pragma unroll
+    for (int k = 0; k < S - 1; ++k)
+        if ((uint64_t)k < nsteps) issue(b_begin + k * kMfmaBlocksPerStep, k);
+
+    uint64_t k = 0;
+    uint32_t slot = 0, fill = S - 1;
+    for (; k + S - 1 < nsteps; ++k) {
+        wait_vmcnt<(S - 2) * kLoadsPerStep>();
+        wg_barrier();
+        issue(b_begin + (k + S - 1) * kMfmaBlocksPerStep, fill);
+        compute_slot(slot);
+        __builtin_amdgcn_sched_barrier(0);
+        slot = slot + 1 == S ? 0 : slot + 1;
+        fill = fill + 1 == S ? 0 : fill + 1;
+    }
+    wait_vmcnt<0>();
+    wg_barrier();
+    for (; k < nsteps; ++k) {
+        compute_slot(slot);
+        slot = slot + 1 == S ? 0 : slot + 1;
+    }
+
+    // ragged tail (fewer than 16 blocks) straight from memory
+    const uint64_t kb = b_begin + nsteps * kMfmaBlocksPerStep;
+    if (kb < b_end) {
+        const u32x4* dl = reinterpret_cast<const u32x4*>(db + ct * 256 + 128 * c + 4 * j);
+        u32x4 bw[4];
+        u32x2 aw[MT];
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+            const uint64_t blk = kb + 4 * g + 2 * h + sl;
+            const bool ok = blk < b_end;
+            bw[2 * sl] = ok ? dl[blk * (block_words / 4)] : u32x4{0, 0, 0, 0};
+            bw[2 * sl + 1] = ok ? dl[blk * (block_words / 4) + 16] : u32x4{0, 0, 0, 0};
+#pragma unroll
+            for (int rt = 0; rt < MT; ++rt) {
+                const uint32_t q = q0 + 16 * rt + j;
+                aw[rt][sl] = (ok && q < p.q_total) ? sel[(uint64_t)q * p.stride_words + blk] : 0u;
+            }
+        }
+        mma(bw, aw);
+    }
+
+    // answer bits: lane holds columns 128c + 64*half + 4j + t' of rows
+    // 16rt + 4g + r; bit 8r + 4*half + t' of par[rt]
+    uint32_t par[MT];
+#pragma unroll
+    for (int rt = 0; rt < MT; ++rt) {
+        par[rt] = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) par[rt] |= (((uint32_t)acc[rt][t][r]) & 1u) << (8 * r + t);
+    }
+    // fold the K halves through LDS (the ring is idle: every load has landed
+    // and, after this barrier, every wave has read its last stage)
+    __syncthreads();
+    u32x4* fold = reinterpret_cast<u32x4*>(pir_ring) + c * 64 + lane;
+    if (h == 1) *fold = u32x4{par[0], par[1], par[2], par[3]};
+    __syncthreads();  // the fold writes are complete and visible
+    if (h == 1) return;
+    const u32x4 o = *fold;
+    par[0] ^= o[0];
+    par[1] ^= o[1];
+    par[2] ^= o[2];
+    par[3] ^= o[3];
+#pragma unroll
+    for (int rt = 0; rt < MT; ++rt) {
+        const uint32_t other = (uint32_t)__shfl_xor((int)par[rt], 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t q = q0 + 16 * rt + 4 * g + r;
+            const uint32_t mine = par[rt] >> (8 * r), theirs = other >> (8 * r);
+            if ((j & 1) == 0 && q < p.q_total) {
+                uint8_t* dst = partials + ((uint64_t)group * p.q_total + q) * p.rpad + ct * 32 + 16 * c + j / 2;
+                dst[0] = (uint8_t)((mine & 0xF) | ((theirs & 0xF) << 4));
+                dst[8] = (uint8_t)(((mine >> 4) & 0xF) | (theirs & 0xF0));
+            }
+        }
+    }
+}
+
 // Stage 2: out[q][m] = XOR over groups of partials[g][q][m].  Each workgroup
 // owns `wpb` consecutive 32-bit words of the [q][rpad] result and splits the
 // groups over 256 / wpb slices, then folds the slices through LDS.
@@ -943,6 +1165,8 @@ bool mfma_supported(uint32_t variant, const Geometry& g, uint32_t qt, uint32_t u
     // 3-stage ring whose selection operand is spread once per workgroup
     // (fp4, 64-query tiles)
     if (unroll == 7) return variant == PIR_VARIANT_MFMA_F4 && qt == 64;
+    // 12, 13, 14 = split-K kernel on a ring of 2, 3, 4 stages (fp4, 64-query tiles)
+    if (unroll >= 12 && unroll <= 14) return variant == PIR_VARIANT_MFMA_F4 && qt == 64;
     if (unroll != 1 && unroll != 2 && unroll != 3 && unroll != 4 && unroll != 6) return false;
     return qt == 16 || qt == 32 || qt == 64;
 }
@@ -959,6 +1183,26 @@ static hipError_t launch_ring(dim3 grid, hipStream_t s, const uint32_t* db, cons
         attr_set = true;
     }
     hipLaunchKernelGGL((k_stage1_mfma_lds<MT, F4, S, SA>), grid, dim3(kThreads), bytes, s, db, sel, partials, p);
+    return hipGetLastError();
+}
+
+// Largest selection pitch (32-bit words) for which the split-K kernel's lane
+// offsets, up to three rows plus 60 bytes, fit in 32 bits.
+constexpr uint64_t kKsMaxStrideWords = ((1ull << 32) - 64) / 12;
+
+template <int S>
+static hipError_t launch_ks(dim3 grid, hipStream_t s, const uint32_t* db, const uint32_t* sel, uint8_t* partials,
+                            const Stage1Params& p) {
+    if (p.stride_words > kKsMaxStrideWords) return launch_ring<4, true, S>(grid, s, db, sel, partials, p);
+    constexpr uint32_t bytes = ring_bytes<4>(S);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage1_mfma_ks<S>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_stage1_mfma_ks<S>), grid, dim3(kThreads), bytes, s, db, sel, partials, p);
     return hipGetLastError();
 }
 
@@ -990,6 +1234,15 @@ static hipError_t launch_mfma_t(const Geometry& g, const Plan& pl, const void* d
         case 6: return launch_ring<MT, F4, 6>(grid, s, d, sel, partials, p);
         case 7:
             if constexpr (MT == 4 && F4) return launch_ring<4, true, 3, true>(grid, s, d, sel, partials, p);
+            return hipErrorInvalidValue;
+        case 12:
+        case 13:
+        case 14:
+            if constexpr (MT == 4 && F4) {
+                if (pl.unroll == 12) return launch_ks<2>(grid, s, d, sel, partials, p);
+                if (pl.unroll == 13) return launch_ks<3>(grid, s, d, sel, partials, p);
+                return launch_ks<4>(grid, s, d, sel, partials, p);
+            }
             return hipErrorInvalidValue;
         default:
             hipLaunchKernelGGL((k_stage1_mfma<MT, F4>), grid, dim3(kThreads), 0, s, d, sel, partials, p);

@@ -749,7 +749,7 @@ int pir_tune(pir_db* d, uint32_t q, pir_kernel_cfg* out) {
     }
     for (uint32_t v : {PIR_VARIANT_MFMA_I8, PIR_VARIANT_MFMA_F4})
         for (uint32_t qt : {16u, 32u, 64u})
-            for (uint32_t u : {1u, 2u, 3u, 4u, 6u, 7u})
+            for (uint32_t u : {1u, 2u, 3u, 4u, 6u, 7u, 12u, 13u, 14u})
                 if (q >= 8 && qt <= qmax_tile && mfma_supported(v, g, qt, u)) cands.push_back({v, qt, u, 0});
     // grid variants of each: the default record-group count, half and double
     std::vector<pir_kernel_cfg> all;

@@ -205,8 +205,9 @@ def test_mfma_variants(ctx, variant, n, r):
     for q in qs:
         d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
         for qt in (16, 32, 64):
-            for unroll in (1, 2, 3, 4, 6, 7):  # registers, LDS rings of 2/3/4/6 stages, shared spread
-                if unroll == 7 and not (variant == pir.PIR_VARIANT_MFMA_F4 and qt == 64):
+            # registers, LDS rings of 2/3/4/6 stages, shared spread, split K on 2/3/4 stages
+            for unroll in (1, 2, 3, 4, 6, 7, 12, 13, 14):
+                if unroll >= 7 and not (variant == pir.PIR_VARIANT_MFMA_F4 and qt == 64):
                     continue
                 for groups in (0, 3, 1):
                     d_out.fill_(0xEE)
@@ -233,9 +234,12 @@ def test_mfma_counts_exact_on_large_group(ctx, variant):
     d_sel = torch.from_numpy(host).to("cuda:0")
     d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
     want3 = oracle.dpxor(dbh, rnd[0])
-    for unroll in (1, 3, 6):
+    cfgs = [(16, 1), (16, 3), (16, 6)]
+    if variant == pir.PIR_VARIANT_MFMA_F4:
+        cfgs.append((64, 13))  # split K: each half's counts and their sum stay exact
+    for qt, unroll in cfgs:
         d_out.fill_(0)
-        db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride, cfg=pir.KernelCfg(variant, 16, unroll, 1))
+        db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride, cfg=pir.KernelCfg(variant, qt, unroll, 1))
         torch.cuda.synchronize()
         got = d_out.cpu().numpy()
         for i in range(q):
