@@ -41,9 +41,9 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
+def kernel_source_hash(src="pir_kernels.hip"):
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2509_06514_amd", "csrc", "pir_kernels.hip"), "rb") as f:
+    with open(os.path.join(ROOT, "paper_2509_06514_amd", "csrc", src), "rb") as f:
         h.update(f.read())
     return h.hexdigest()[:16]
 
@@ -166,6 +166,57 @@ def cpu_baseline(db_host, sel_rows, n, r, sample_queries, threads):
 #     40 + 448 rounds 2-8 + 16 round 9 (column 0) + 6 last round (byte 0) + 10 = 623
 DPF_OPS_FULL = 737
 DPF_OPS_LEAF = 623
+
+
+VARIANT_NAME = {1: "valu_select_xor", 2: "mfma_int8", 3: "mfma_fp4"}
+
+
+def variant_sweep(ctx, db, d_sel, stride, n, r, q, d_out, torch, pir, reps=3):
+    """Best stage-1 time of each kernel family (vector-ALU select-XOR, int8 and fp4 matrix
+    cores) for this Q over a fixed candidate list (default record groups), and whether every
+    candidate returned the same bytes."""
+    import numpy as np
+    p2 = 1 << max(0, (q - 1).bit_length())
+    fams = {1: [], 2: [], 3: []}
+    for qt in (1, 2, 4, 8, 16, 32):
+        if min(p2, 8) <= qt <= p2:
+            fams[1] += [(qt, u) for u in (2, 4, 8)]
+    if q >= 8:
+        for v in (2, 3):
+            for qt in (16, 32, 64):
+                if qt <= max(p2, 16):
+                    fams[v] += [(qt, u) for u in (2, 3, 4) + ((12, 13, 14) if v == 3 and qt == 64 else ())]
+    ref, same, out = None, True, {}
+    for v, cands in fams.items():
+        best = None
+        for qt, u in cands:
+            cfg = pir.KernelCfg(v, qt, u, 0)
+            try:
+                d_out.fill_(0xEE)
+                db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride, cfg=cfg)
+                torch.cuda.synchronize()
+            except pir.PirError:
+                continue
+            got = d_out.cpu().numpy()
+            if ref is None:
+                ref = got.copy()
+            elif not np.array_equal(got, ref):
+                same = False
+            ctx.timing(True)
+            ctx.timing_read(reset=True)
+            for _ in range(reps):
+                db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride, cfg=cfg)
+            torch.cuda.synchronize()
+            t = ctx.timing_read(reset=True)
+            ctx.timing(False)
+            ms = t["stage1_ms"] / max(1, t["stage1_launches"])
+            if best is None or ms < best[0]:
+                best = (ms, cfg)
+        if best is not None:
+            out[VARIANT_NAME[v]] = {"cfg": best[1].as_dict(), "stage1_ms": best[0], "candidates": len(cands),
+                                    "roofline": roofline_for(v, n, r, q, best[0], None)}
+            log(f"variants Q={q}: {VARIANT_NAME[v]} best {best[0]:.3f} ms {best[1]}")
+    return {"families": out, "identical_answers": same, "reps": reps}
 
 
 def dpf_bench(ctx, db, db_host, n, r, args, torch, pir):
@@ -296,7 +347,8 @@ def fp_bench(ctx, args, torch, pir):
         rec = {"ms_per_pass": wall / args.steps * 1e3, "queries_per_s": qq * args.steps / wall,
                "latency_ms": {"p50": percentile(per, 0.5), "p99": percentile(per, 0.99)},
                "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": ach / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": alg,
+                            "frac": ach / HBM_PEAK_GBS, "traffic": load_fp_traffic(qq, L),
+                            "algorithmic_bytes_per_launch": alg,
                             "avg_launch_ms": s1}}
         if qq == q:
             out.update(rec)
@@ -315,6 +367,25 @@ def fp_bench(ctx, args, torch, pir):
                                          f"{dt:.2f} s"}
     db.free()
     return out
+
+
+def load_fp_traffic(q, L):
+    """HBM bytes per launch of the F_p stage-1 kernel from the committed counter runs, if they are
+    for this source and kernel instance; else None."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic_fp_n24.json")) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    entry = t.get(f"q{q}")
+    if not entry or t.get("kernel_source_sha256_16") != kernel_source_hash("pir_fp.hip"):
+        return None
+    rt = 1 if q <= 16 else 2 if q <= 32 else 4
+    n_ct = (L + 15) // 16
+    ct = 4 if n_ct >= 4 else 2 if n_ct >= 2 else 1
+    if entry.get("kernel") != f"k_fp_stage1_lds<{rt}, {ct}>":
+        return None
+    return entry.get("hbm_bytes_per_launch")
 
 
 SERVE_DBS = [(1 << 23, 32), (1 << 24, 128), (1 << 22, 1024)]
@@ -343,6 +414,15 @@ def serve_bench(args):
         dbs.append(ctx.load_db(h))
         hosts.append(h)
         log(f"serve: loaded DB{k} N={n} R={r}")
+    # tune every batch-size bucket (powers of two up to q_max) the server can form
+    for k, d in enumerate(dbs):
+        qq = 1
+        while True:
+            d.tune(min(qq, args.serve_qmax))
+            if qq >= args.serve_qmax:
+                break
+            qq *= 2
+        log(f"serve: tuned DB{k} for batches of 1 .. {args.serve_qmax}")
     pool = [synth.selections(n, 16, seed=synth.S_SEL + 50 + k) for k, (n, r) in enumerate(SERVE_DBS)]
     if args.serve_keys:
         # requests are DPF keys: a pool per database (the server's cost does not
@@ -364,9 +444,6 @@ def serve_bench(args):
         srv = pir.Server(ctx, q_max=args.serve_qmax, max_wait_us=args.serve_wait_us, n_slots=args.serve_slots,
                          queue_cap=1 << 20)
         ids = [srv.add_db(d) for d in dbs]
-        # warm the plans for every batch size the server can form
-        for d in dbs:
-            d.tune(args.serve_qmax)
         outs = [np.zeros((4096, r), np.uint8) for (n, r) in SERVE_DBS]
         # at least 10 s or 20k requests per rate (whichever comes first), at least serve_seconds
         dur = min(10.0, max(args.serve_seconds, 20000.0 / rate))
@@ -441,6 +518,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c4", choices=sorted(CONFIGS))
     ap.add_argument("--no-tune", action="store_true", help="use the default kernel plan")
+    ap.add_argument("--variants", action="store_true",
+                    help="also time the best plan of each kernel family (VALU, int8 MFMA, fp4 MFMA) for Q")
     ap.add_argument("--cpu-sample", type=int, default=2, help="oracle queries for cpu_baseline (0 = skip)")
     ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1),
                     help="host threads for the all-core oracle baseline (one query each)")
@@ -606,6 +685,9 @@ def main():
     # is covered by the tests; here only that the answers are not all zero
     ans = d_out.cpu().numpy()
     result["answers_nonzero"] = bool(ans.any())
+
+    if args.variants:
+        result["variants"] = variant_sweep(ctx, db, d_sel, stride, n, r, q, d_out, torch, pir)
 
     if args.dpf_keys > 0:
         result["dpf"] = dpf_bench(ctx, db, db_host, n, r, args, torch, pir)

@@ -28,10 +28,11 @@ typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kFpThreads = 256;  // 4 waves; the waves of a workgroup split its K-steps
 
-// Operand source for query rows and column tiles that fall outside the
-// problem: every load of the main loop is unconditional (so the compiler can
-// count the loads in flight), and masked operands read zeros from here.
+// Operand source for column tiles that fall outside the problem (and, at
+// g_zero128, for query rows past the last one): the main loop's loads are
+// unconditional, masked operands read zeros from here.
 __device__ uint8_t g_zero64[64];
+__device__ __attribute__((aligned(16))) uint8_t g_zero128[128];
 
 __device__ __forceinline__ u32x4 ld16(const uint8_t* p) {
     return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
@@ -43,127 +44,6 @@ __device__ __forceinline__ uint32_t mod_p(uint32_t x, uint32_t p, uint32_t m) {
     const uint32_t q = __umulhi(x, m);
     uint32_t r = x - q * p;
     return r >= p ? r - p : r;
-}
-
-// Stage 1: workgroup = (record group g, query tile qt, column group cg).
-// RT row tiles of 16 queries, CT column tiles of 16 elements.  A wave step
-// covers KT consecutive tiles (KT * 64 contiguous bytes of every query row);
-// the waves of a workgroup take the steps of its range in turn.  The four
-// waves' sums (each reduced mod p) meet in LDS; one byte per (group, query,
-// element) is written: partials[(g * q_total + q) * L + c].
-template <int RT, int CT, int KT>
-__global__ void __launch_bounds__(kFpThreads)
-k_fp_stage1(const uint8_t* __restrict__ db, const uint8_t* __restrict__ v, uint8_t* __restrict__ partials,
-            FpParams a) {
-    __shared__ uint32_t red[RT * CT * 4 * 64];
-    for (uint32_t i = threadIdx.x; i < RT * CT * 4 * 64; i += kFpThreads) red[i] = 0;
-
-    const uint32_t g = blockIdx.x % a.groups;
-    const uint32_t rest = blockIdx.x / a.groups;
-    const uint32_t qt = rest % a.n_qt, cg = rest / a.n_qt;
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t row = lane & 15, kq = lane >> 4;
-
-    const uint64_t t0 = (uint64_t)g * a.tiles_per_group;
-    const uint64_t t1 = t0 + a.tiles_per_group < a.tiles ? t0 + a.tiles_per_group : a.tiles;
-
-    // A operand: query row q0 + 16 rt + row, record bytes 16 kq .. 16 kq + 15
-    // of a tile; B operand: column 16 c + row of the tile, records
-    // 16 kq .. 16 kq + 15.  Masked rows / column tiles read zeros (step 0).
-    const uint8_t* abase[RT];
-    uint64_t astep[RT];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-        const uint32_t q = qt * 16 * RT + 16 * rt + row;
-        const bool ok = q < a.q_total;
-        abase[rt] = ok ? v + (uint64_t)q * a.v_stride + 16 * kq : g_zero64 + 16 * kq;
-        astep[rt] = ok ? 64 : 0;
-    }
-    const uint64_t tile_bytes = 64ull * a.lpad;
-    const uint8_t* bbase[CT];
-    uint64_t bstep[CT];
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-        const uint32_t c = cg * CT + ct;
-        const bool ok = c < a.n_ct;
-        bbase[ct] = ok ? db + c * 1024 + row * 64 + 16 * kq : g_zero64 + 16 * kq;
-        bstep[ct] = ok ? tile_bytes : 0;
-    }
-
-    i32x4 acc[RT][CT];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = i32x4{0, 0, 0, 0};
-
-    // every load is unconditional: tiles past the range are clamped to the
-    // last one (their products are skipped below)
-    u32x4 A[KT][RT], B[KT][CT], An[KT][RT], Bn[KT][CT];
-    auto load = [&](uint64_t t, u32x4(&ra)[KT][RT], u32x4(&rb)[KT][CT]) {
-#pragma unroll
-        for (int k = 0; k < KT; ++k) {
-            const uint64_t tk = t + k < t1 ? t + k : t1 - 1;
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt) ra[k][rt] = ld16(abase[rt] + tk * astep[rt]);
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct) rb[k][ct] = ld16(bbase[ct] + tk * bstep[ct]);
-        }
-    };
-    auto compute = [&](uint64_t t, const u32x4(&ra)[KT][RT], const u32x4(&rb)[KT][CT]) {
-        // keep the loads issued before this point ahead of the matrix work
-        asm volatile("" ::: "memory");
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int k = 0; k < KT; ++k) {
-            if (k > 0 && t + k >= t1) break;  // uniform: the range ends inside this step
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                for (int ct = 0; ct < CT; ++ct)
-                    acc[rt][ct] =
-                        __builtin_amdgcn_mfma_i32_16x16x64_i8((i32x4)ra[k][rt], (i32x4)rb[k][ct], acc[rt][ct], 0, 0, 0);
-        }
-    };
-
-    // Two register sets in turn: the next step's loads are in flight while a
-    // step runs on the matrix cores.  Wave w takes the steps starting at
-    // t0 + KT (w + 4 i); the step after the last reloads it (unconditional).
-    constexpr uint64_t kStride = 4 * KT;
-    uint64_t t = t0 + KT * wave;
-    if (t < t1) {
-        load(t, A, B);
-        for (;;) {
-            const uint64_t t2 = t + kStride;
-            load(t2 < t1 ? t2 : t, An, Bn);
-            compute(t, A, B);
-            if (t2 >= t1) break;
-            const uint64_t t3 = t2 + kStride;
-            load(t3 < t1 ? t3 : t2, A, B);
-            compute(t2, An, Bn);
-            if (t3 >= t1) break;
-            t = t3;
-        }
-    }
-
-    // 16x16 MFMA tile: lane holds column lane % 16 and rows 4 (lane / 16) + r
-    __syncthreads();  // red[] cleared
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                atomicAdd(&red[((rt * CT + ct) * 4 + r) * 64 + lane], mod_p((uint32_t)acc[rt][ct][r], a.p, a.magic));
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < RT * CT * 4 * 64; i += kFpThreads) {
-        const uint32_t ln = i & 63, r = (i >> 6) & 3, tc = i >> 8;
-        const uint32_t rt = tc / CT, ct = tc % CT;
-        const uint32_t q = qt * 16 * RT + 16 * rt + 4 * (ln >> 4) + r;
-        const uint32_t c = (cg * CT + ct) * 16 + (ln & 15);
-        if (q < a.q_total && c < a.L)
-            partials[((uint64_t)g * a.q_total + q) * a.L + c] = (uint8_t)mod_p(red[i], a.p, a.magic);
-    }
 }
 
 // Stage 2, in two levels so that no thread walks all groups (with few
@@ -234,31 +114,221 @@ k_fp_untile(const uint8_t* __restrict__ src, uint64_t nrec, uint32_t L, uint32_t
     dst[i] = src[(j / 64) * 64ull * lpad + c * 64ull + (j % 64)];
 }
 
-template <int RT, int CT, int KT>
-hipError_t launch_rt_ct(const uint8_t* db, const uint8_t* v, uint8_t* partials, const FpParams& a, uint32_t grid,
-                        hipStream_t s) {
-    hipLaunchKernelGGL((k_fp_stage1<RT, CT, KT>), dim3(grid), dim3(kFpThreads), 0, s, db, v, partials, a);
+// s_waitcnt vmcnt(<= N), other counters not waited for (gfx9 encoding).
+template <int N>
+__device__ __forceinline__ void fp_wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+// Stage 1: workgroup = (record group g, query tile qt, column group cg), RT
+// row tiles of 16 queries, CT column tiles of 16 elements.  A wave step
+// covers two tiles (128 records: one whole 128-byte line of every query row
+// of the tile); the four waves of a workgroup take the steps of its range in
+// turn, and their sums (each reduced mod p) meet in LDS.  One byte per
+// (group, query, element) is written: partials[(g * q_total + q) * L + c].
+//
+// The query rows go through LDS.  Read straight into the MFMA layout, a
+// lane's A operand is 16 bytes of one row and a load instruction would touch
+// 64 bytes of each of 16 rows: half of every line, the other half going to
+// another instruction.  Here each direct-to-LDS load (global_load_lds_dwordx4)
+// moves 8 rows x 128 bytes into a wave-private LDS buffer, and the operands
+// are read from there.  Two buffers per wave: the next step's lines are in
+// flight while a step runs.  Row 8i + r, 16-byte chunk c of the line sits at
+// i * 1 KiB + 128 * (c ^ (i & 1)) + 16 r: the XOR spreads the 16 rows that
+// one operand read touches over all LDS banks.  The database operand (whole
+// lines in the tile layout) is loaded into registers.
+//
+// Workgroups are numbered XCD-major, as in the XOR scan: the query tiles and
+// column groups of one record group run on one XCD, close together in time,
+// and share its L2 copy of the record tiles.
+template <int RT, int CT>
+__host__ __device__ constexpr uint32_t fp_lds_bytes() {
+    return 4u * 2u * (16u * RT * 128u) + RT * CT * 4u * 64u * 4u;
+}
+
+template <int RT, int CT>
+__global__ void __launch_bounds__(kFpThreads)
+k_fp_stage1_lds(const uint8_t* __restrict__ db, const uint8_t* __restrict__ v, uint8_t* __restrict__ partials,
+                FpParams a) {
+    constexpr int kRows = 16 * RT;
+    constexpr int kAInstr = kRows / 8;  // direct-to-LDS loads per step (8 rows x 128 B each)
+    constexpr int kLoadsPerStep = kAInstr + 2 * CT;
+    constexpr uint32_t kBuf = kRows * 128;
+    extern __shared__ __attribute__((aligned(16))) uint8_t fp_lds[];
+    uint32_t* const red = reinterpret_cast<uint32_t*>(fp_lds + 4 * 2 * kBuf);
+
+    const uint32_t total = a.groups * a.n_qt * a.n_cg;
+    const uint32_t per_xcd = (total + 7) / 8;
+    const uint32_t vb = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (vb >= total) return;  // grid padding (whole workgroup)
+    const uint32_t qt = vb % a.n_qt;
+    const uint32_t cg = (vb / a.n_qt) % a.n_cg;
+    const uint32_t g = vb / (a.n_qt * a.n_cg);
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t row = lane & 15, kq = lane >> 4;
+    uint8_t* const bufs = fp_lds + wave * 2 * kBuf;
+    for (uint32_t i = threadIdx.x; i < RT * CT * 4 * 64; i += kFpThreads) red[i] = 0;
+
+    const uint64_t t0 = (uint64_t)g * a.tiles_per_group;
+    const uint64_t t1 = t0 + a.tiles_per_group < a.tiles ? t0 + a.tiles_per_group : a.tiles;
+
+    // loader: instruction i, lane l -> row 8i + (l & 7), chunk (l >> 3) ^ (i & 1)
+    const uint8_t* abase[kAInstr];
+    uint32_t astep[kAInstr], achunk[kAInstr];
+#pragma unroll
+    for (int i = 0; i < kAInstr; ++i) {
+        const uint32_t q = qt * kRows + 8 * i + (lane & 7);
+        const bool ok = q < a.q_total;
+        abase[i] = ok ? v + (uint64_t)q * a.v_stride : g_zero128;
+        astep[i] = ok ? 64 : 0;
+        achunk[i] = (lane >> 3) ^ (i & 1);
+    }
+    const uint64_t tile_bytes = 64ull * a.lpad;
+    const uint8_t* bbase[CT];
+    uint64_t bstep[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+        const uint32_t c = cg * CT + ct;
+        const bool ok = c < a.n_ct;
+        bbase[ct] = ok ? db + c * 1024 + row * 64 + 16 * kq : g_zero64 + 16 * kq;
+        bstep[ct] = ok ? tile_bytes : 0;
+    }
+    // this lane's A operand of half h, row tile rt: row 16 rt + row, chunk 4h + kq
+    uint32_t rd[2][RT];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const uint32_t i = 2 * rt + (row >> 3);
+            rd[h][rt] = i * 1024 + 128 * ((4 * h + kq) ^ (i & 1)) + 16 * (row & 7);
+        }
+
+    i32x4 acc[RT][CT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = i32x4{0, 0, 0, 0};
+
+    // a step at tile t covers t and t + 1 (when t + 1 < t1; otherwise the
+    // second half re-reads the first, in bounds, and its products are skipped)
+    auto issue = [&](uint64_t t, uint32_t b, u32x4(&rb)[2][CT]) {
+        const bool two = t + 1 < t1;
+        uint8_t* dst = bufs + b * kBuf;
+#pragma unroll
+        for (int i = 0; i < kAInstr; ++i) {
+            const uint32_t ch = (two || achunk[i] < 4) ? achunk[i] : achunk[i] - 4;
+            __builtin_amdgcn_global_load_lds(
+                reinterpret_cast<const uint32_t*>(abase[i] + t * astep[i] + 16 * ch), dst + i * 1024, 16, 0, 0);
+        }
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            rb[0][ct] = ld16(bbase[ct] + t * bstep[ct]);
+            rb[1][ct] = ld16(bbase[ct] + (two ? t + 1 : t) * bstep[ct]);
+        }
+    };
+    auto compute = [&](uint64_t t, uint32_t b, const u32x4(&rb)[2][CT]) {
+        const uint8_t* src = bufs + b * kBuf;
+        const int halves = t + 1 < t1 ? 2 : 1;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h >= halves) break;  // uniform
+            u32x4 ra[RT];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) ra[rt] = *reinterpret_cast<const u32x4*>(src + rd[h][rt]);
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct)
+                    acc[rt][ct] =
+                        __builtin_amdgcn_mfma_i32_16x16x64_i8((i32x4)ra[rt], (i32x4)rb[h][ct], acc[rt][ct], 0, 0, 0);
+        }
+    };
+
+    // Wave w takes the steps at t0 + 2 (w + 4 i).  Each step waits for its own
+    // loads (vmcnt) with the next step's in flight; a buffer is refilled only
+    // after the step that read it has finished its LDS reads.
+    constexpr uint64_t kStride = 8;
+    uint64_t t = t0 + 2 * wave;
+    if (t < t1) {
+        u32x4 B0[2][CT], B1[2][CT];
+        issue(t, 0, B0);
+        for (;;) {
+            uint64_t t2 = t + kStride;
+            if (t2 >= t1) {
+                fp_wait_vmcnt<0>();
+                compute(t, 0, B0);
+                break;
+            }
+            issue(t2, 1, B1);
+            fp_wait_vmcnt<kLoadsPerStep>();
+            compute(t, 0, B0);
+            __builtin_amdgcn_sched_barrier(0);
+            const uint64_t t3 = t2 + kStride;
+            if (t3 >= t1) {
+                fp_wait_vmcnt<0>();
+                compute(t2, 1, B1);
+                break;
+            }
+            issue(t3, 0, B0);
+            fp_wait_vmcnt<kLoadsPerStep>();
+            compute(t2, 1, B1);
+            __builtin_amdgcn_sched_barrier(0);
+            t = t3;
+        }
+    }
+
+    __syncthreads();  // red[] cleared
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                atomicAdd(&red[((rt * CT + ct) * 4 + r) * 64 + lane], mod_p((uint32_t)acc[rt][ct][r], a.p, a.magic));
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < RT * CT * 4 * 64; i += kFpThreads) {
+        const uint32_t ln = i & 63, r = (i >> 6) & 3, tc = i >> 8;
+        const uint32_t rt = tc / CT, ct = tc % CT;
+        const uint32_t q = qt * kRows + 16 * rt + 4 * (ln >> 4) + r;
+        const uint32_t c = (cg * CT + ct) * 16 + (ln & 15);
+        if (q < a.q_total && c < a.L)
+            partials[((uint64_t)g * a.q_total + q) * a.L + c] = (uint8_t)mod_p(red[i], a.p, a.magic);
+    }
+}
+
+template <int RT, int CT>
+hipError_t launch_lds_rt_ct(const uint8_t* db, const uint8_t* v, uint8_t* partials, const FpParams& a,
+                            uint32_t grid, hipStream_t s) {
+    constexpr uint32_t bytes = fp_lds_bytes<RT, CT>();
+    static bool attr_set = false;  // the dynamic-LDS limit is raised once per instance
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fp_stage1_lds<RT, CT>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_fp_stage1_lds<RT, CT>), dim3(grid), dim3(kFpThreads), bytes, s, db, v, partials, a);
     return hipGetLastError();
 }
 
+
 }  // namespace
 
-bool fp_supported(uint32_t rt, uint32_t ct, uint32_t kt) {
-    return (rt == 1 || rt == 2 || rt == 4) && (ct == 1 || ct == 2 || ct == 4) && (kt == 1 || kt == 2);
+bool fp_supported(uint32_t rt, uint32_t ct) {
+    return (rt == 1 || rt == 2 || rt == 4) && (ct == 1 || ct == 2 || ct == 4);
 }
 
 hipError_t launch_fp_stage1(const uint8_t* db, const uint8_t* v, uint8_t* partials, const FpParams& a, uint32_t rt,
-                            uint32_t ct, uint32_t kt, hipStream_t s) {
-    const uint32_t grid = a.groups * a.n_qt * a.n_cg;
-#define PIR_FP_CASE(R_, C_, K_) \
-    if (rt == R_ && ct == C_ && kt == K_) return launch_rt_ct<R_, C_, K_>(db, v, partials, a, grid, s);
-#define PIR_FP_CASES(K_) \
-    PIR_FP_CASE(1, 1, K_) PIR_FP_CASE(1, 2, K_) PIR_FP_CASE(1, 4, K_) \
-    PIR_FP_CASE(2, 1, K_) PIR_FP_CASE(2, 2, K_) PIR_FP_CASE(2, 4, K_) \
-    PIR_FP_CASE(4, 1, K_) PIR_FP_CASE(4, 2, K_) PIR_FP_CASE(4, 4, K_)
-    PIR_FP_CASES(1)
-    PIR_FP_CASES(2)
-#undef PIR_FP_CASES
+                            uint32_t ct, hipStream_t s) {
+    const uint32_t total = a.groups * a.n_qt * a.n_cg;
+    const uint32_t grid = (total + 7) / 8 * 8;
+#define PIR_FP_CASE(R_, C_) \
+    if (rt == R_ && ct == C_) return launch_lds_rt_ct<R_, C_>(db, v, partials, a, grid, s);
+    PIR_FP_CASE(1, 1) PIR_FP_CASE(1, 2) PIR_FP_CASE(1, 4)
+    PIR_FP_CASE(2, 1) PIR_FP_CASE(2, 2) PIR_FP_CASE(2, 4)
+    PIR_FP_CASE(4, 1) PIR_FP_CASE(4, 2) PIR_FP_CASE(4, 4)
 #undef PIR_FP_CASE
     return hipErrorInvalidValue;
 }

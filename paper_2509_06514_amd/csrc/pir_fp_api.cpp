@@ -32,14 +32,14 @@ uint64_t chunk_records(uint32_t L) {
     return r < 64 ? 64 : r;
 }
 
+// Workgroups a launch aims for (record groups x query tiles x column groups).
+constexpr uint64_t kFpTargetWorkgroups = 2048;
+
 // Plan for q queries: row tiles of 16 queries (up to 4), column tiles of 16
-// elements (up to 4), record groups so that about 2048 workgroups run.  With
-// one row tile and 8+ queries a wave step covers two tiles (128 contiguous
-// bytes of each query row: 4.7 instead of 4.5 TB/s at 16 queries); with more
-// row tiles the larger register sets cost more occupancy than that gains.
-void fp_plan(const FpDb& db, uint32_t q, FpParams& a, uint32_t& rt, uint32_t& ct, uint32_t& kt) {
+// elements (up to 4), record groups so that about kFpTargetWorkgroups
+// workgroups run, each group an even number of tiles.
+void fp_plan(const FpDb& db, uint32_t q, FpParams& a, uint32_t& rt, uint32_t& ct) {
     rt = q <= 16 ? 1 : q <= 32 ? 2 : 4;
-    kt = (rt == 1 && q >= 8) ? 2 : 1;
     const uint32_t n_ct = db.lpad / 16;
     ct = n_ct >= 4 ? 4 : n_ct >= 2 ? 2 : 1;
     a.tiles = db.tiles;
@@ -51,18 +51,20 @@ void fp_plan(const FpDb& db, uint32_t q, FpParams& a, uint32_t& rt, uint32_t& ct
     a.q_total = q;
     a.p = db.p;
     a.magic = db.magic;
-    uint64_t g = (2048 + a.n_qt * a.n_cg - 1) / (a.n_qt * a.n_cg);
+    uint64_t g = (kFpTargetWorkgroups + a.n_qt * a.n_cg - 1) / (a.n_qt * a.n_cg);
     g = std::max<uint64_t>(g, (db.tiles + kFpMaxTilesPerGroup - 1) / kFpMaxTilesPerGroup);
     g = std::min<uint64_t>(g, db.tiles);
     a.tiles_per_group = (db.tiles + g - 1) / g;
+    // even, so that every wave step starts on a 128-byte line of the query rows
+    a.tiles_per_group = std::min<uint64_t>((a.tiles_per_group + 1) & ~1ull, kFpMaxTilesPerGroup);
     a.groups = (uint32_t)((db.tiles + a.tiles_per_group - 1) / a.tiles_per_group);
 }
 
 int enqueue_fp(FpDb& db, const uint8_t* d_v, uint64_t v_stride, uint32_t q, uint8_t* d_out, DevBuf& ws,
                hipStream_t s, bool may_sync) {
     FpParams a;
-    uint32_t rt, ct, kt;
-    fp_plan(db, q, a, rt, ct, kt);
+    uint32_t rt, ct;
+    fp_plan(db, q, a, rt, ct);
     a.v_stride = v_stride;
     const size_t part_bytes = ((size_t)a.groups * q * db.L + 255) / 256 * 256;
     const size_t need = part_bytes + fp_stage2_tmp_bytes(a.groups, (uint64_t)q * db.L);
@@ -83,7 +85,7 @@ int enqueue_fp(FpDb& db, const uint8_t* d_v, uint64_t v_stride, uint32_t q, uint
         e1 = ctx->take_event();
     }
     if (e0) (void)hipEventRecord(e0, s);
-    hipError_t e = launch_fp_stage1((const uint8_t*)db.data.ptr, d_v, (uint8_t*)ws.ptr, a, rt, ct, kt, s);
+    hipError_t e = launch_fp_stage1((const uint8_t*)db.data.ptr, d_v, (uint8_t*)ws.ptr, a, rt, ct, s);
     if (e != hipSuccess) return hip_fail(e, "F_p stage-1 launch");
     if (e1) (void)hipEventRecord(e1, s);
     e = launch_fp_stage2((const uint8_t*)ws.ptr, a.groups, (uint64_t)q * db.L, db.p, db.magic,

@@ -100,13 +100,14 @@ struct FpParams {
     uint32_t groups = 0, n_qt = 0, n_cg = 0;
     uint32_t q_total = 0, p = 0, magic = 0;  // magic = floor(2^32 / p)
 };
-// A wave sums every 4th tile of its group: 2^31 / (64 * 127 * 126) > 2048
-// tiles per wave, so 8192 tiles per group keep every int32 sum exact.
+// A wave sums a quarter of its group's tiles (two of every eight):
+// 2^31 / (64 * 127 * 126) > 2048 tiles per wave, so 8192 tiles per group keep
+// every int32 sum exact.
 constexpr uint64_t kFpMaxTilesPerGroup = 8192;
-bool fp_supported(uint32_t rt, uint32_t ct, uint32_t kt);
-// rt row tiles (16 queries each), ct column tiles (16 elements each), kt tiles per wave step
+bool fp_supported(uint32_t rt, uint32_t ct);
+// rt row tiles (16 queries each), ct column tiles (16 elements each)
 hipError_t launch_fp_stage1(const uint8_t* db, const uint8_t* v, uint8_t* partials, const FpParams& a, uint32_t rt,
-                            uint32_t ct, uint32_t kt, hipStream_t s);
+                            uint32_t ct, hipStream_t s);
 // cross-group reduction: tmp holds fp_stage2_tmp_bytes(groups, outputs)
 size_t fp_stage2_tmp_bytes(uint32_t groups, uint64_t outputs);
 hipError_t launch_fp_stage2(const uint8_t* partials, uint32_t groups, uint64_t outputs, uint32_t p, uint32_t magic,

@@ -345,6 +345,12 @@ int Ctx::plan_for(const Db& db, uint32_t q, const pir_kernel_cfg* cfg, Plan& p) 
             base.qt = it->second.q_tile;
             base.unroll = it->second.unroll;
             base.groups = it->second.groups;
+        } else if (q >= 8 && mfma_supported(PIR_VARIANT_MFMA_F4, db.geo, 16, 4)) {
+            // untuned: from 8 queries up the fp4 matrix cores (the split-K
+            // kernel for 64-query tiles), as the tuner picks on MI355X
+            base.variant = PIR_VARIANT_MFMA_F4;
+            base.qt = q <= 16 ? 16 : (q <= 32 ? 32 : 64);
+            base.unroll = base.qt == 64 ? 12 : 4;
         } else {
             base.variant = PIR_VARIANT_VALU;
         }
@@ -747,10 +753,13 @@ int pir_tune(pir_db* d, uint32_t q, pir_kernel_cfg* out) {
         for (uint32_t u : {1u, 2u, 4u, 8u, 16u})
             if (valu_supported(qt, u)) cands.push_back({PIR_VARIANT_VALU, qt, u, 0});
     }
+    // matrix-core tiles are at least 16 queries: from 8 queries up, one
+    // 16-query tile with idle rows is still worth timing
     for (uint32_t v : {PIR_VARIANT_MFMA_I8, PIR_VARIANT_MFMA_F4})
         for (uint32_t qt : {16u, 32u, 64u})
             for (uint32_t u : {1u, 2u, 3u, 4u, 6u, 7u, 12u, 13u, 14u})
-                if (q >= 8 && qt <= qmax_tile && mfma_supported(v, g, qt, u)) cands.push_back({v, qt, u, 0});
+                if (q >= 8 && qt <= std::max<uint32_t>(qmax_tile, 16) && mfma_supported(v, g, qt, u))
+                    cands.push_back({v, qt, u, 0});
     // grid variants of each: the default record-group count, half and double
     std::vector<pir_kernel_cfg> all;
     for (auto c : cands) {
@@ -824,13 +833,14 @@ int pir_tune(pir_db* d, uint32_t q, pir_kernel_cfg* out) {
             best_cfg = done;
         }
     }
-    // Final round: the candidates within 5 % of the best (at most 6) again,
-    // round-robin so that they share the device's clock and thermal state;
+    // Final round: the candidates within 10 % of the best (at most 8) again,
+    // round-robin so that they share the device's clock and thermal state
+    // (the first round's probes are minutes apart on a slow candidate list);
     // the lowest median of 4 rounds of 4 launches wins.
     std::sort(timed.begin(), timed.end(), [](const Timed& x, const Timed& y) { return x.ms < y.ms; });
     std::vector<Timed> fin;
     for (const Timed& t : timed)
-        if (t.ms <= 1.05f * best && fin.size() < 6) fin.push_back(t);
+        if (t.ms <= 1.10f * best && fin.size() < 8) fin.push_back(t);
     if (fin.size() > 1) {
         std::vector<std::vector<float>> samples(fin.size());
         for (int round = 0; round < 4; ++round)
