@@ -33,6 +33,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 
@@ -358,6 +359,53 @@ k_dpf_expand(const uint8_t* __restrict__ keys, uint32_t key_bytes, uint32_t n, u
     if (BITS) out_bits[q * bits_stride + i] = word;
 }
 
+// The top T levels of every key's tree in one workgroup per key (blockIdx.x),
+// breadth-first: at level a each of the first count(a) threads expands one
+// node (eq. 3) into an LDS buffer, a barrier, the next level.  count(a) =
+// ceil(n_leaves / 2^(n - a)) nodes lead to leaves below n_leaves.  The
+// children of level T - 1 go to out_nodes (row q), where the launch chain
+// continues.  This replaces T single-level launches near the root, whose
+// cost is launch latency, not work.  Dynamic LDS: the lookup table at
+// address 0 (the kernel has no static LDS), then two node buffers of BS.
+template <int BS>
+__global__ void __launch_bounds__(BS)
+k_dpf_top(const uint8_t* __restrict__ keys, uint32_t key_bytes, uint32_t n, uint64_t n_leaves, uint32_t T,
+          u32x4* __restrict__ out_nodes, uint64_t out_stride) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t dpf_dyn[];
+    uint32_t* const s_tab = dpf_dyn;
+    u32x4* const nodes = reinterpret_cast<u32x4*>(dpf_dyn + kTabBytes / 4);
+    for (uint32_t m = threadIdx.x; m < kTabBytes / 16; m += BS) {
+        const uint32_t v0 = c_te0[m >> 4];
+        const uint32_t v = (m & 8) ? rotr(v0, 16) : v0;  // second half of the row: Te2
+        reinterpret_cast<u32x4*>(s_tab)[m] = u32x4{v, v, v, v};
+    }
+    const uint32_t q = blockIdx.x;
+    const u32x4* kq = reinterpret_cast<const u32x4*>(keys + (uint64_t)q * key_bytes);
+    const uint32_t n1 = n + 1;
+    const Lut L{s_tab, (threadIdx.x & 31u) * 4u, 128u + (threadIdx.x & 31u) * 4u};
+    if (threadIdx.x == 0) nodes[0] = kq[0];  // eq. 2 at the root
+    __syncthreads();
+    for (uint32_t a = 0; a < T; ++a) {
+        const uint32_t sh = n - a;
+        const uint64_t cnt = (n_leaves + (1ull << sh) - 1) >> sh;
+        const u32x4* src = nodes + (a & 1) * BS;
+        u32x4* dst = nodes + ((a + 1) & 1) * BS;
+        const bool last = a + 1 == T;
+        for (uint32_t i = threadIdx.x; i < cnt; i += BS) {
+            u32x4 c0, c1;
+            expand(L, kq, n1, a + 1, src[i], c0, c1);
+            if (last) {
+                out_nodes[q * out_stride + 2 * i] = c0;
+                out_nodes[q * out_stride + 2 * i + 1] = c1;
+            } else {
+                dst[2 * i] = c0;
+                dst[2 * i + 1] = c1;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ host side
@@ -376,13 +424,18 @@ uint64_t dpf_key_bytes(uint32_t n) { return 64ull * (n + 1); }
 
 static inline uint64_t ceil_shift(uint64_t x, uint32_t s) { return (x + (1ull << s) - 1) >> s; }
 
-// The chain of launches for a 2^n domain as (a, E) pairs; the last one writes
-// bits.  Near the root, where a level has few nodes, a launch expands one to
-// three levels (its latency is E sequential expansions per thread); below,
-// five.
-int dpf_plan(uint32_t n, uint64_t n_leaves, uint32_t n_keys, uint32_t steps[][2]) {
+// Levels the top kernel expands for a 2^n domain (0: none).  Level T must
+// still be at most n - 5 (the chain's last launch expands five levels, or
+// the whole tree for n <= 5), and 2^(T-1) nodes fit in a node buffer.
+uint32_t dpf_top_levels(uint32_t n) { return n > 5 ? std::min<uint32_t>(kDpfTopLevels, n - 5) : 0; }
+
+// The chain of launches from level a0 for a 2^n domain as (a, E) pairs; the
+// last one writes bits.  Near the root, where a level has few nodes, a launch
+// expands one to three levels (its latency is E sequential expansions per
+// thread); below, five.
+int dpf_plan(uint32_t n, uint64_t n_leaves, uint32_t n_keys, uint32_t a0, uint32_t steps[][2]) {
     int ns = 0;
-    uint32_t a = 0;
+    uint32_t a = a0;
     while (n > a + 5) {
         const uint64_t threads = ceil_shift(n_leaves, n - a) * n_keys;
         uint32_t E = threads < 4096 ? 1 : threads < 65536 ? 2 : threads < (1u << 19) ? 3 : 5;
@@ -422,18 +475,36 @@ hipError_t launch_dpf_eval(int device, const uint8_t* d_keys, uint32_t n, uint32
     hipError_t e = setup_device(device);
     if (e != hipSuccess) return e;
     uint32_t steps[64][2];
-    const int ns = dpf_plan(n, n_leaves, n_keys, steps);
+    const uint32_t T = dpf_top_levels(n);
+    const int ns = dpf_plan(n, n_leaves, n_keys, T, steps);
     const uint32_t kb = (uint32_t)dpf_key_bytes(n);
     u32x4* buf[2] = {reinterpret_cast<u32x4*>(scratch),
                      reinterpret_cast<u32x4*>(scratch) + (uint64_t)n_keys * scratch_nodes};
     // `in` always points into the scratch (the a = 0 launch reads the root
     // from the key instead, but a valid pointer keeps any load in bounds)
     const u32x4* in = buf[1];
+    int slot = 0;  // buffer the next launch writes
+    if (T > 0) {
+        constexpr uint32_t bytes = kTabBytes + 2 * kDpfTopThreads * 16;
+        static bool attr_set = false;  // the dynamic-LDS limit is raised once
+        if (!attr_set) {
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dpf_top<kDpfTopThreads>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+            if (e != hipSuccess) return e;
+            attr_set = true;
+        }
+        hipLaunchKernelGGL((k_dpf_top<kDpfTopThreads>), dim3(n_keys), dim3(kDpfTopThreads), bytes, s, d_keys, kb, n,
+                           n_leaves, T, buf[0], scratch_nodes);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        in = buf[0];
+        slot = 1;
+    }
     for (int k = 0; k < ns; ++k) {
         const uint32_t a = steps[k][0], E = steps[k][1];
         const uint64_t count = ceil_shift(n_leaves, n - a);
         const bool bits = k + 1 == ns;
-        u32x4* out = bits ? nullptr : buf[k & 1];
+        u32x4* out = bits ? nullptr : buf[slot];
+        slot ^= 1;
         // large launches: 1024-thread workgroups, one per CU, share one table
         // copy between 16 waves; small ones: 256 threads, spread over more CUs
         if (count * n_keys >= kDpfBigLaunch)

@@ -78,8 +78,13 @@ constexpr uint64_t kDpfBigLaunch = 256 * 1024;  // threads from which DPF launch
 uint64_t dpf_key_bytes(uint32_t n);
 // nodes per key in each of the two scratch buffers of an evaluation
 uint64_t dpf_scratch_nodes(uint32_t n, uint64_t n_leaves);
-// launch chain as (first level, levels expanded); returns the number of launches
-int dpf_plan(uint32_t n, uint64_t n_leaves, uint32_t n_keys, uint32_t steps[][2]);
+// top of the tree in one workgroup per key: up to this many levels, by
+// kDpfTopThreads threads (2^(levels - 1) <= kDpfTopThreads)
+constexpr uint32_t kDpfTopLevels = 10;
+constexpr int kDpfTopThreads = 1024;
+uint32_t dpf_top_levels(uint32_t n);
+// launch chain from level a0 as (first level, levels expanded); returns the number of launches
+int dpf_plan(uint32_t n, uint64_t n_leaves, uint32_t n_keys, uint32_t a0, uint32_t steps[][2]);
 // full-domain evaluation of n_keys keys (device, dpf_key_bytes(n) apart):
 // selection words [0, ceil(n_leaves / 32)) of row q at d_sel + q * stride_words;
 // scratch holds 2 * n_keys * scratch_nodes 16-byte nodes
