@@ -486,13 +486,8 @@ hipError_t launch_dpf_eval(int device, const uint8_t* d_keys, uint32_t n, uint32
     int slot = 0;  // buffer the next launch writes
     if (T > 0) {
         constexpr uint32_t bytes = kTabBytes + 2 * kDpfTopThreads * 16;
-        static bool attr_set = false;  // the dynamic-LDS limit is raised once
-        if (!attr_set) {
-            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dpf_top<kDpfTopThreads>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-            if (e != hipSuccess) return e;
-            attr_set = true;
-        }
+        e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_dpf_top<kDpfTopThreads>), (int)bytes);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_dpf_top<kDpfTopThreads>), dim3(n_keys), dim3(kDpfTopThreads), bytes, s, d_keys, kb, n,
                            n_leaves, T, buf[0], scratch_nodes);
         if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -302,13 +302,8 @@ template <int RT, int CT>
 hipError_t launch_lds_rt_ct(const uint8_t* db, const uint8_t* v, uint8_t* partials, const FpParams& a,
                             uint32_t grid, hipStream_t s) {
     constexpr uint32_t bytes = fp_lds_bytes<RT, CT>();
-    static bool attr_set = false;  // the dynamic-LDS limit is raised once per instance
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fp_stage1_lds<RT, CT>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_fp_stage1_lds<RT, CT>), (int)bytes);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_fp_stage1_lds<RT, CT>), dim3(grid), dim3(kFpThreads), bytes, s, db, v, partials, a);
     return hipGetLastError();
 }

@@ -9,6 +9,10 @@
 
 namespace pir {
 
+// Raise a kernel's dynamic-LDS limit to `bytes` on the current device, once
+// per (kernel, device); safe to call from several host threads.
+hipError_t ensure_dynamic_lds(const void* kernel, int bytes);
+
 // Geometry of a bit-sliced database.
 //
 // Records are grouped in blocks of 32.  Block blk is 8*R 32-bit words; word b

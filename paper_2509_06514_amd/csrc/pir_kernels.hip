@@ -1175,13 +1175,8 @@ template <int MT, bool F4, int S, bool SA = false>
 static hipError_t launch_ring(dim3 grid, hipStream_t s, const uint32_t* db, const uint32_t* sel, uint8_t* partials,
                               const Stage1Params& p) {
     constexpr uint32_t bytes = ring_bytes<MT>(S) + (SA ? 16u * 1024u : 0u);
-    static bool attr_set = false;  // the dynamic-LDS limit is raised once per instance
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage1_mfma_lds<MT, F4, S, SA>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_lds<MT, F4, S, SA>), (int)bytes);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_stage1_mfma_lds<MT, F4, S, SA>), grid, dim3(kThreads), bytes, s, db, sel, partials, p);
     return hipGetLastError();
 }
@@ -1195,13 +1190,8 @@ static hipError_t launch_ks(dim3 grid, hipStream_t s, const uint32_t* db, const 
                             const Stage1Params& p) {
     if (p.stride_words > kKsMaxStrideWords) return launch_ring<4, true, S>(grid, s, db, sel, partials, p);
     constexpr uint32_t bytes = ring_bytes<4>(S);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage1_mfma_ks<S>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ks<S>), (int)bytes);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_stage1_mfma_ks<S>), grid, dim3(kThreads), bytes, s, db, sel, partials, p);
     return hipGetLastError();
 }
