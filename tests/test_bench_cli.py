@@ -1,0 +1,40 @@
+"""bench.py's host-side contract (no GPU): the one-GPU limit and the names it
+reports for the kernel a plan launches."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+import paper_2509_06514_amd as pir  # noqa: E402
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU only" in (r.stdout + r.stderr)
+
+
+@pytest.mark.parametrize("cfg,r,name", [
+    ((1, 1, 8, 0), 32, "k_stage1_valu<1, 8, false>"),
+    ((1, 8, 2, 0), 16, "k_stage1_valu<8, 2, true>"),
+    ((3, 64, 3, 0), 32, "k_stage1_mfma_lds<4, true, 3, false>"),
+    ((2, 16, 4, 0), 32, "k_stage1_mfma_lds<1, false, 4, false>"),
+    ((3, 64, 7, 0), 32, "k_stage1_mfma_lds<4, true, 3, true>"),
+    ((3, 64, 12, 0), 32, "k_stage1_mfma_ks<2>"),
+    ((3, 64, 14, 0), 32, "k_stage1_mfma_ks<4>"),
+    ((3, 32, 1, 0), 32, "k_stage1_mfma<2, true>"),
+])
+def test_kernel_names_follow_the_plan(cfg, r, name):
+    assert bench.kernel_name(pir.KernelCfg(*cfg), r) == name
+
+
+def test_kernel_names_exist_in_the_source():
+    src = open(os.path.join(ROOT, "paper_2509_06514_amd", "csrc", "pir_kernels.hip")).read()
+    for kernel in ("k_stage1_valu", "k_stage1_mfma_lds", "k_stage1_mfma_ks", "k_stage1_mfma"):
+        assert f"\n{kernel}(" in src, kernel
