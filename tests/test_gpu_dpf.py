@@ -61,7 +61,7 @@ def _oracle_bits(key, n, count):
     return out
 
 
-@pytest.mark.parametrize("n", [0, 1, 2, 3, 4, 5, 6, 7, 9, 12, 14])
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 4, 5, 6, 7, 9, 12, 14, 15, 16])  # 15, 16: ten top levels in one launch
 def test_eval_full_domain_matches_oracle(ctx, n):
     # two Gen keys and two keys with random codewords, whole domain
     r0, r1 = _roots(synth.S_KEY + n)
@@ -77,7 +77,7 @@ def test_eval_full_domain_matches_oracle(ctx, n):
     assert x.sum() == 1 and x[alpha] == 1
 
 
-@pytest.mark.parametrize("n,n_leaves", [(10, 1000), (11, 1025), (13, 5000), (6, 33), (5, 7)])
+@pytest.mark.parametrize("n,n_leaves", [(10, 1000), (11, 1025), (13, 5000), (6, 33), (5, 7), (17, 100003)])
 def test_eval_ragged_leaf_count(ctx, n, n_leaves):
     # words [0, ceil(n_leaves/32)) are written, the padding of the row is not touched
     keys = _random_keys(n, 3, synth.S_KEY + 200 + n)
