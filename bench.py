@@ -547,7 +547,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the scan shards by queries or by record ranges, see DESIGN.md)", file=sys.stderr)
+              "(across GPUs the scan would shard by queries or by record ranges)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
