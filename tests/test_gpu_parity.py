@@ -247,3 +247,22 @@ def test_mfma_counts_exact_on_large_group(ctx, variant):
                 assert np.array_equal(got[i], want_all), (unroll, i)
         assert np.array_equal(got[3], want3), unroll
     db.free()
+
+
+def test_largest_batch(ctx):
+    # Q = PIR_MAX_BATCH queries in one call: 64 query tiles of the matrix-core
+    # form, the vector-ALU form and the synchronous host path give the oracle's rows
+    n, r, q = 5003, 32, 4096
+    dbh = synth.database(n, r, seed=0x4096)
+    db = ctx.load_db(dbh)
+    sel = synth.selections(n, q, seed=0x4097)
+    want = oracle.dpxor_batch(dbh, sel)
+    d_sel, stride = _dev_rows(sel, n)
+    d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
+    for cfg in (None, pir.KernelCfg(pir.PIR_VARIANT_VALU, 32, 2, 0), pir.KernelCfg(pir.PIR_VARIANT_MFMA_I8, 64, 3, 0)):
+        d_out.fill_(0xEE)
+        db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride, cfg=cfg)
+        torch.cuda.synchronize()
+        assert np.array_equal(d_out.cpu().numpy(), want), cfg
+    assert np.array_equal(db.dpxor_batch(sel[:, : (n + 7) // 8]), want)
+    db.free()
