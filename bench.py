@@ -284,6 +284,22 @@ def dpf_bench(ctx, db, db_host, n, r, args, torch, pir):
     out["key_to_answer"] = {"queries_per_s": nk * args.dpf_steps / wall_a,
                             "ms_per_call": wall_a / args.dpf_steps * 1e3, "two_server_check": bool(ok_a)}
     log(f"keys -> answers: {out['key_to_answer']['queries_per_s']:.1f} q/s, two-server check {ok_a}")
+
+    # the same with the last tree level and the scan in one kernel
+    d_fused = torch.empty((nk, r), dtype=torch.uint8, device="cuda:0")
+
+    def step_fused():
+        db.dpf_dpxor_async(d_keys, nk, d_fused, fused=True)
+
+    step_fused()
+    torch.cuda.synchronize()
+    wall_f, _ = time_steps(step_fused, args.dpf_steps, torch)
+    fused = d_fused.cpu().numpy()
+    out["key_to_answer_fused"] = {"queries_per_s": nk * args.dpf_steps / wall_f,
+                                  "ms_per_call": wall_f / args.dpf_steps * 1e3,
+                                  "same_as_pipeline": bool(np.array_equal(fused, ans))}
+    log(f"keys -> answers, fused: {out['key_to_answer_fused']['queries_per_s']:.1f} q/s, "
+        f"same as the pipeline {out['key_to_answer_fused']['same_as_pipeline']}")
     if args.cpu_sample > 0:
         out["cpu_baseline"] = dpf_cpu_baseline(keys[0])
     return out

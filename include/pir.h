@@ -367,6 +367,18 @@ int pir_dpf_eval_async(pir_ctx* ctx, const void* d_keys, uint32_t n, uint32_t n_
 int pir_dpf_dpxor_async(pir_db* db, const void* d_keys, uint32_t n_keys, void* d_out, void* hip_stream);
 
 /*
+ * The same answers with the evaluation's last level and the scan in one
+ * kernel (Sec. 3.2 then Sec. 3.3, the leaves consumed where they are made):
+ * each thread expands the 32 leaves of one 32-record block and the wave
+ * applies them to its 64 blocks of the database at once, so no selection
+ * bits are written to or read from memory.  The database is read once per
+ * key (the batched scan of pir_dpf_dpxor_async reads it once per 64 keys).
+ * Same arguments, layout and workspace rules as pir_dpf_dpxor_async;
+ * record_bytes must be at most 4096 (PIR_E_INVAL otherwise).
+ */
+int pir_dpf_dpxor_fused_async(pir_db* db, const void* d_keys, uint32_t n_keys, void* d_out, void* hip_stream);
+
+/*
  * Client side, host only: the record from the two servers' answers
  * (Algorithm 1, client step: D[i] = r1 XOR r2).  out may alias either
  * input.  Errors: PIR_E_INVAL for NULL pointers.

@@ -13,6 +13,16 @@ namespace pir {
 // per (kernel, device); safe to call from several host threads.
 hipError_t ensure_dynamic_lds(const void* kernel, int bytes);
 
+// Stored word order.  Inside every nibble of a bit-sliced word the records
+// 4n and 4n+2 trade places (an involution): stored bit 4n+2 is record 4n and
+// stored bit 4n is record 4n+2.  This lets the matrix-core spread of a
+// database word use masks for three of its four parts.  A selection word,
+// which arrives in record order, is brought to stored order with the same
+// swap before it meets a stored word bit for bit.
+__host__ __device__ inline uint32_t nib_swap02(uint32_t x) {
+    return (x & 0xAAAAAAAAu) | ((x & 0x11111111u) << 2) | ((x >> 2) & 0x11111111u);
+}
+
 // Geometry of a bit-sliced database.
 //
 // Records are grouped in blocks of 32.  Block blk is 8*R 32-bit words; word b
@@ -92,9 +102,20 @@ int dpf_plan(uint32_t n, uint64_t n_leaves, uint32_t n_keys, uint32_t a0, uint32
 // full-domain evaluation of n_keys keys (device, dpf_key_bytes(n) apart):
 // selection words [0, ceil(n_leaves / 32)) of row q at d_sel + q * stride_words;
 // scratch holds 2 * n_keys * scratch_nodes 16-byte nodes
+// Where the last launch of an evaluation scans instead of writing bits: the
+// bit-sliced database (16-byte chunks, cpb per block) and the partial
+// answers, kDpfScanSlots x n_keys rows of rpad bytes (as 32-bit words) that
+// the launch zeroes and then XORs into; R <= kDpfScanMaxR.
+constexpr uint32_t kDpfScanSlots = 64;
+constexpr uint32_t kDpfScanMaxR = 4096;  // 64 KiB of table + 16 waves x rpad bytes within 160 KiB of LDS
+struct DpfScanOut {
+    const void* db;
+    uint32_t cpb, R, rpad;
+    uint32_t* acc;
+};
 hipError_t launch_dpf_eval(int device, const uint8_t* d_keys, uint32_t n, uint32_t n_keys, uint64_t n_leaves,
                            uint32_t* d_sel, uint64_t stride_words, void* scratch, uint64_t scratch_nodes,
-                           hipStream_t s);
+                           hipStream_t s, const DpfScanOut* scan = nullptr);
 void dpf_gen_host(uint64_t alpha, uint32_t n, const uint8_t root0[16], const uint8_t root1[16], uint8_t* key0,
                   uint8_t* key1);
 void aes128_encrypt_host(const uint8_t key[16], const uint8_t in[16], uint8_t out[16]);

@@ -65,16 +65,6 @@ __device__ __forceinline__ void sel_xor(u32x4& acc, const u32x4& d, uint32_t s) 
     acc.w = xor_and(acc.w, d.w, s);
 }
 
-// Stored word order.  Inside every nibble of a bit-sliced word the records
-// 4n and 4n+2 trade places (an involution): stored bit 4n+2 is record 4n and
-// stored bit 4n is record 4n+2.  This lets the matrix-core spread of a
-// database word use masks for three of its four parts (spread_fp4_b).  A
-// selection word, which arrives in record order, is brought to stored order
-// with the same swap before it meets a stored word bit for bit.
-__device__ __forceinline__ uint32_t nib_swap02(uint32_t x) {
-    return (x & 0xAAAAAAAAu) | ((x & 0x11111111u) << 2) | ((x >> 2) & 0x11111111u);
-}
-
 // Workgroup -> (record group, column tile, query tile).  Workgroups are
 // dispatched round-robin over the 8 XCDs; consecutive workgroups on one XCD
 // get the column/query tiles of the same record group, so the selection
