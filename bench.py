@@ -219,6 +219,37 @@ def variant_sweep(ctx, db, d_sel, stride, n, r, q, d_out, torch, pir, reps=3):
     return {"families": out, "identical_answers": same, "reps": reps}
 
 
+def host_path_bench(db, sel_host, n, r, q, steps, pir):
+    """The synchronous host calls (selection upload, scan, answer download),
+    with pageable and with pinned (pir_host_alloc) buffers: PCIe-inclusive
+    rates, reported beside the resident-input figures, never in their place."""
+    import numpy as np
+    row = (n + 7) // 8
+    res = {"steps": steps, "sel_bytes_per_query": row}
+    for qq in (1, q):
+        src = sel_host[:qq, :row]  # host pitch = ceil(N/8): one contiguous upload per query
+        page_sel = np.ascontiguousarray(src)
+        page_out = np.empty((qq, r), np.uint8)
+        pin_sel = pir.pinned_empty((qq, row))
+        pin_sel[:] = src
+        pin_out = pir.pinned_empty((qq, r))
+        entry = {}
+        for name, a, o in (("pageable", page_sel, page_out), ("pinned", pin_sel, pin_out)):
+            db.dpxor_batch(a, out=o)  # warm-up: staging buffers, plan, graph
+            t = time.perf_counter()
+            for _ in range(steps):
+                db.dpxor_batch(a, out=o)
+            ms = (time.perf_counter() - t) / steps * 1e3
+            entry[name] = {"ms_per_call": ms, "queries_per_s": qq / ms * 1e3,
+                           "sel_gbs": qq * row / (ms / 1e3) / 1e9}
+        assert np.array_equal(pin_out, page_out)
+        res[f"q{qq}"] = entry
+        log(f"host path Q={qq}: pageable {entry['pageable']['ms_per_call']:.2f} ms, "
+            f"pinned {entry['pinned']['ms_per_call']:.2f} ms per call")
+        del pin_sel, pin_out
+    return res
+
+
 def dpf_bench(ctx, db, db_host, n, r, args, torch, pir):
     """DPF evaluation on the database's domain and answers straight from keys."""
     import numpy as np
@@ -545,6 +576,8 @@ def main():
     ap.add_argument("--serve-key-rates", default="500,1000,2000,4000",
                     help="offered rates for --serve-keys (each key costs a full-domain evaluation)")
     ap.add_argument("--no-single", action="store_true", help="skip the single-query pass")
+    ap.add_argument("--host-steps", type=int, default=3,
+                    help="calls per case of the synchronous host-buffer path (0 = skip)")
     ap.add_argument("--dpf-keys", type=int, default=8,
                     help="DPF keys (pairs of parties) evaluated per call in the DPF section (0 = skip)")
     ap.add_argument("--dpf-steps", type=int, default=5)
@@ -701,6 +734,9 @@ def main():
     # is covered by the tests; here only that the answers are not all zero
     ans = d_out.cpu().numpy()
     result["answers_nonzero"] = bool(ans.any())
+
+    if args.host_steps > 0:
+        result["host_path"] = host_path_bench(db, sel_host, n, r, q, args.host_steps, pir)
 
     if args.variants:
         result["variants"] = variant_sweep(ctx, db, d_sel, stride, n, r, q, d_out, torch, pir)

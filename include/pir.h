@@ -127,7 +127,9 @@ int pir_dpxor(pir_db* db, const uint8_t* sel_bits, uint8_t* out_record);
 /*
  * Q queries in one database pass, synchronous.  sel_bits holds q rows
  * sel_stride bytes apart (sel_stride >= ceil(N/8)); out receives q rows of R
- * bytes.  1 <= q <= PIR_MAX_BATCH.
+ * bytes.  1 <= q <= PIR_MAX_BATCH.  Pinned buffers (pir_host_alloc) are
+ * copied to and from the device directly; pageable ones go through the
+ * library's pinned staging, in chunks whose packing overlaps the upload.
  */
 int pir_dpxor_batch(pir_db* db, const uint8_t* sel_bits, uint64_t sel_stride, uint32_t q,
                     uint8_t* out);
@@ -431,7 +433,8 @@ int pir_fp_inner(pir_fpdb* db, const uint8_t* v, uint64_t v_stride, uint32_t q, 
 
 /* ---------------------------------------------------------------- memory */
 
-/* Pinned host memory (hipHostMalloc); NULL on failure. */
+/* Pinned host memory (hipHostMalloc); NULL on failure.  The synchronous
+ * calls copy pinned selection and answer buffers without staging. */
 void* pir_host_alloc(size_t bytes);
 void pir_host_free(void* p);
 

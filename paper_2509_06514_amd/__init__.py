@@ -5,6 +5,7 @@ scan runs in the library's HIP kernels; this module only marshals arguments.
 torch supplies device buffers and streams for the asynchronous calls.
 """
 import ctypes
+import weakref
 
 import numpy as np
 
@@ -13,7 +14,7 @@ from ._native import (PIR_MAX_BATCH, PIR_VARIANT_AUTO, PIR_VARIANT_MFMA_F4, PIR_
                       PIR_VARIANT_VALU, PirError, check, lib)
 
 __all__ = ["Context", "Database", "FpDatabase", "Server", "KernelCfg", "PirError", "lib", "sel_stride_for",
-           "dpf_key_bytes", "dpf_domain_bits", "dpf_gen", "reconstruct",
+           "dpf_key_bytes", "dpf_domain_bits", "dpf_gen", "reconstruct", "pinned_empty",
            "PIR_MAX_BATCH", "PIR_VARIANT_AUTO", "PIR_VARIANT_VALU", "PIR_VARIANT_MFMA_I8",
            "PIR_VARIANT_MFMA_F4"]
 
@@ -65,6 +66,23 @@ def sel_stride_for(n_records, align=256):
     """Device selection-row pitch: whole 32-bit words for ceil(N/32) blocks, aligned."""
     words = (n_records + 31) // 32
     return (4 * words + align - 1) // align * align
+
+
+def pinned_empty(shape, dtype=np.uint8):
+    """A numpy array in pinned host memory (pir_host_alloc), freed with the array.
+
+    The synchronous calls copy such buffers to and from the device without
+    staging them.
+    """
+    dtype = np.dtype(dtype)
+    count = int(np.prod(shape, dtype=np.int64))
+    nbytes = max(count * dtype.itemsize, 1)
+    p = lib().pir_host_alloc(nbytes)
+    if not p:
+        raise MemoryError(f"pir_host_alloc({nbytes}) failed")
+    buf = (ctypes.c_uint8 * nbytes).from_address(p)
+    weakref.finalize(buf, lib().pir_host_free, ctypes.c_void_p(p))
+    return np.frombuffer(buf, dtype=dtype, count=count).reshape(shape)
 
 
 def dpf_key_bytes(n):
@@ -204,20 +222,35 @@ class Database:
     def sel_row_bytes(self):
         return (self.n_records + 7) // 8
 
-    def dpxor(self, sel):
-        """One query, host in/out: sel packed bits (>= ceil(N/8) bytes) -> R-byte answer."""
+    def _host_out(self, out, shape):
+        if out is None:
+            return np.empty(shape, np.uint8)
+        if out.dtype != np.uint8 or out.shape != shape or not out.flags.c_contiguous:
+            raise ValueError(f"out must be a C-contiguous uint8 array of shape {shape}")
+        return out
+
+    def dpxor(self, sel, out=None):
+        """One query, host in/out: sel packed bits (>= ceil(N/8) bytes) -> R-byte answer.
+
+        Arrays from pinned_empty (for sel and out) skip the library's staging copies.
+        """
         sel = _u8(sel).reshape(-1)
         if sel.size < self.sel_row_bytes:
             raise ValueError("selection shorter than ceil(N/8) bytes")
-        out = np.empty(self.record_bytes, np.uint8)
+        out = self._host_out(out, (self.record_bytes,))
         check(lib().pir_dpxor(self._h, _ptr(sel), _ptr(out)), "pir_dpxor")
         return out
 
-    def dpxor_batch(self, sel_rows):
-        """Q queries, host in/out: sel_rows (Q, stride) uint8 -> (Q, R) answers."""
+    def dpxor_batch(self, sel_rows, out=None):
+        """Q queries, host in/out: sel_rows (Q, stride) uint8 -> (Q, R) answers.
+
+        Arrays from pinned_empty (for sel_rows and out) skip the library's staging copies.
+        """
         sel_rows = _u8(sel_rows)
         q, stride = sel_rows.shape
-        out = np.empty((q, self.record_bytes), np.uint8)
+        if stride < self.sel_row_bytes:
+            raise ValueError("selection rows shorter than ceil(N/8) bytes")
+        out = self._host_out(out, (q, self.record_bytes))
         check(lib().pir_dpxor_batch(self._h, _ptr(sel_rows), stride, q, _ptr(out)), "pir_dpxor_batch")
         return out
 

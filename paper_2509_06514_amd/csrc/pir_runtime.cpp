@@ -167,6 +167,8 @@ Ctx::~Ctx() {
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
     for (auto& e : pool) {
         if (e->stream) (void)hipStreamDestroy(e->stream);
+        for (hipEvent_t ev : e->staged)
+            if (ev) (void)hipEventDestroy(ev);
     }
     pool.clear();
     for (auto& kv : workspaces) kv.second.reset();
@@ -201,6 +203,15 @@ int Ctx::acquire(Exec** out) {
     auto e = std::make_unique<Exec>();
     hipError_t he = hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking);
     if (he != hipSuccess) return hip_fail(he, "hipStreamCreate");
+    for (hipEvent_t& ev : e->staged) {
+        he = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (he != hipSuccess) {
+            for (hipEvent_t x : e->staged)
+                if (x) (void)hipEventDestroy(x);
+            (void)hipStreamDestroy(e->stream);
+            return hip_fail(he, "hipEventCreate");
+        }
+    }
     e->busy = true;
     *out = e.get();
     pool.push_back(std::move(e));
@@ -672,7 +683,32 @@ int pir_dpxor_batch_async(pir_db* d, const void* d_sel, uint64_t sel_stride, uin
     return pir_dpxor_batch_async_cfg(d, d_sel, sel_stride, q, d_out, hip_stream, nullptr);
 }
 
-// Synchronous path: pack host rows into pinned staging, upload, scan, download.
+// Whether [p, p + bytes) is pinned host memory (pir_host_alloc / hipHostMalloc)
+// that the device can copy from or to directly.  A pageable pointer makes the
+// query fail; its error is cleared so later launch checks do not see it.
+static bool pinned_host(const void* p, size_t bytes) {
+    for (const void* x : {p, (const void*)((const uint8_t*)p + (bytes ? bytes - 1 : 0))}) {
+        hipPointerAttribute_t a;
+        if (hipPointerGetAttributes(&a, x) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        if (a.type != hipMemoryTypeHost) return false;
+    }
+    return true;
+}
+
+// Rows per staging half for the pageable path (about 16 MiB, at least one).
+static uint32_t stage_rows(uint64_t dstride) {
+    const uint64_t r = (16ull << 20) / dstride;
+    return r < 1 ? 1u : (uint32_t)r;
+}
+
+// Synchronous path: upload, scan, download on a pooled stream.  Pinned
+// selection rows (and a pinned answer buffer) are copied straight to (from)
+// the device with a pitched copy; pageable rows are packed into two pinned
+// staging halves in turn, so that packing one chunk of rows overlaps the
+// upload of the previous one.
 int pir_dpxor_batch(pir_db* d, const uint8_t* sel_bits, uint64_t sel_stride, uint32_t q, uint8_t* out) {
     clear_error();
     Db* db = reinterpret_cast<Db*>(d);
@@ -699,23 +735,51 @@ int pir_dpxor_batch(pir_db* d, const uint8_t* sel_bits, uint64_t sel_stride, uin
     } rel{ctx, ex};
     const uint64_t dstride = (4ull * g.nb + 255) / 256 * 256;  // device row pitch
     const size_t sel_bytes = (size_t)dstride * q, out_bytes = (size_t)g.R * q;
+    const bool sel_pinned = pinned_host(sel_bits, (size_t)sel_stride * (q - 1) + row_bytes);
+    const bool out_pinned = pinned_host(out, out_bytes);
     hipError_t e;
-    if ((e = ex->h_sel.ensure(sel_bytes)) != hipSuccess) return hip_fail(e, "pinned selection staging");
     if ((e = ex->d_sel.ensure(sel_bytes)) != hipSuccess) return hip_fail(e, "device selection buffer");
-    if ((e = ex->h_out.ensure(out_bytes)) != hipSuccess) return hip_fail(e, "pinned answer staging");
     if ((e = ex->d_out.ensure(out_bytes)) != hipSuccess) return hip_fail(e, "device answer buffer");
     if ((e = ex->partials.ensure(partial_bytes(g, p, q))) != hipSuccess) return hip_fail(e, "workspace");
-    uint8_t* hs = (uint8_t*)ex->h_sel.ptr;
-    for (uint32_t i = 0; i < q; ++i) {
-        uint8_t* row = hs + (size_t)i * dstride;
-        memcpy(row, sel_bits + (size_t)i * sel_stride, row_bytes);
-        memset(row + row_bytes, 0, dstride - row_bytes);
+    uint8_t* const ds = (uint8_t*)ex->d_sel.ptr;
+    if (sel_pinned) {
+        // row tails past ceil(N/8) bytes are never read by the scans
+        if ((e = hipMemcpy2DAsync(ds, dstride, sel_bits, sel_stride, row_bytes, q, hipMemcpyHostToDevice,
+                                  ex->stream)) != hipSuccess)
+            return hip_fail(e, "selection upload");
+    } else {
+        const uint32_t rows = std::min<uint32_t>(q, stage_rows(dstride));
+        if ((e = ex->h_sel.ensure((size_t)2 * rows * dstride)) != hipSuccess)
+            return hip_fail(e, "pinned selection staging");
+        for (uint32_t r0 = 0, c = 0; r0 < q; r0 += rows, ++c) {
+            const uint32_t nr = std::min<uint32_t>(rows, q - r0);
+            const int half = c & 1;
+            // the upload that last used this half has finished
+            if (c >= 2 && (e = hipEventSynchronize(ex->staged[half])) != hipSuccess)
+                return hip_fail(e, "selection staging");
+            uint8_t* hs = (uint8_t*)ex->h_sel.ptr + (size_t)half * rows * dstride;
+            for (uint32_t i = 0; i < nr; ++i) {
+                uint8_t* row = hs + (size_t)i * dstride;
+                memcpy(row, sel_bits + (size_t)(r0 + i) * sel_stride, row_bytes);
+                memset(row + row_bytes, 0, dstride - row_bytes);
+            }
+            if ((e = hipMemcpyAsync(ds + (size_t)r0 * dstride, hs, (size_t)nr * dstride, hipMemcpyHostToDevice,
+                                    ex->stream)) != hipSuccess)
+                return hip_fail(e, "selection upload");
+            if ((e = hipEventRecord(ex->staged[half], ex->stream)) != hipSuccess)
+                return hip_fail(e, "selection staging");
+        }
     }
-    if ((e = hipMemcpyAsync(ex->d_sel.ptr, hs, sel_bytes, hipMemcpyHostToDevice, ex->stream)) != hipSuccess)
-        return hip_fail(e, "selection upload");
-    rc = ctx->launch_scan(*db, p, (const uint32_t*)ex->d_sel.ptr, dstride / 4, q, (uint8_t*)ex->d_out.ptr,
+    rc = ctx->launch_scan(*db, p, (const uint32_t*)ds, dstride / 4, q, (uint8_t*)ex->d_out.ptr,
                            (uint8_t*)ex->partials.ptr, ex->stream);
     if (rc) return rc;
+    if (out_pinned) {
+        if ((e = hipMemcpyAsync(out, ex->d_out.ptr, out_bytes, hipMemcpyDeviceToHost, ex->stream)) != hipSuccess)
+            return hip_fail(e, "answer download");
+        if ((e = hipStreamSynchronize(ex->stream)) != hipSuccess) return hip_fail(e, "scan");
+        return PIR_OK;
+    }
+    if ((e = ex->h_out.ensure(out_bytes)) != hipSuccess) return hip_fail(e, "pinned answer staging");
     if ((e = hipMemcpyAsync(ex->h_out.ptr, ex->d_out.ptr, out_bytes, hipMemcpyDeviceToHost, ex->stream)) !=
         hipSuccess)
         return hip_fail(e, "answer download");

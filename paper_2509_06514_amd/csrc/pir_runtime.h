@@ -50,6 +50,7 @@ struct Exec {
     bool busy = false;
     HostBuf h_sel, h_out;
     DevBuf d_sel, d_out, partials;
+    hipEvent_t staged[2] = {nullptr, nullptr};  // uploads out of the two staging halves
 };
 
 struct TimedPair {

@@ -266,3 +266,31 @@ def test_largest_batch(ctx):
         assert np.array_equal(d_out.cpu().numpy(), want), cfg
     assert np.array_equal(db.dpxor_batch(sel[:, : (n + 7) // 8]), want)
     db.free()
+
+
+def test_host_path_pinned_and_staged(ctx):
+    # The synchronous call with pageable rows (packed into two pinned halves,
+    # 4 rows of this database's 4 MiB device pitch per half, so 11 rows take
+    # three chunks and reuse the first half) and with pinned rows and answers
+    # (pitched copies straight to and from the device): same bytes as the
+    # oracle, for an odd host stride and junk past N in every row.
+    n, r, q = (1 << 25) + 77, 8, 11
+    stride = (n + 7) // 8 + 3
+    dbh = synth.database(n, r, seed=0x5717)
+    db = ctx.load_db(dbh)
+    sel = synth.selections(n, q, seed=0x5718, stride=stride, tail_junk=True)
+    want = oracle.dpxor_batch(dbh, sel)
+    assert np.array_equal(db.dpxor_batch(sel), want)
+    p_sel = pir.pinned_empty((q, stride))
+    p_out = pir.pinned_empty((q, r))
+    synth.selections(n, q, seed=0x5718, stride=stride, tail_junk=True, out=p_sel)
+    p_out.fill(0xEE)
+    assert db.dpxor_batch(p_sel, out=p_out) is p_out
+    assert np.array_equal(p_out, want)
+    assert np.array_equal(db.dpxor_batch(p_sel), want)  # pinned in, pageable out
+    assert np.array_equal(db.dpxor_batch(sel, out=p_out), want)  # pageable in, pinned out
+    assert np.array_equal(db.dpxor_batch(p_sel[:5]), want[:5])  # fewer rows on the same buffers
+    p_one = pir.pinned_empty((r,))
+    assert np.array_equal(db.dpxor(p_sel[3], out=p_one), want[3])
+    assert np.array_equal(db.dpxor(sel[7]), want[7])
+    db.free()
