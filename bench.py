@@ -60,6 +60,8 @@ def kernel_name(cfg, r):
         return f"k_stage1_mfma_lds<{mt}, {f4}, 3, true>"
     if 12 <= cfg.unroll <= 14:  # split K on a ring of 2/3/4 stages
         return f"k_stage1_mfma_ks<{cfg.unroll - 10}>"
+    if cfg.unroll == 15:  # split K, 2-stage ring, selection words 4 K-steps at a time
+        return "k_stage1_mfma_ksw"
     return f"k_stage1_mfma<{mt}, {f4}>"
 
 
@@ -185,7 +187,7 @@ def variant_sweep(ctx, db, d_sel, stride, n, r, q, d_out, torch, pir, reps=3):
         for v in (2, 3):
             for qt in (16, 32, 64):
                 if qt <= max(p2, 16):
-                    fams[v] += [(qt, u) for u in (2, 3, 4) + ((12, 13, 14) if v == 3 and qt == 64 else ())]
+                    fams[v] += [(qt, u) for u in (2, 3, 4) + ((12, 13, 14, 15) if v == 3 and qt == 64 else ())]
     ref, same, out = None, True, {}
     for v, cands in fams.items():
         best = None

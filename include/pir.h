@@ -156,7 +156,9 @@ typedef struct pir_kernel_cfg {
                          2/3/4/6 = LDS ring of that many stages, 7 = 3-stage ring with the
                          selection operand spread once per workgroup (fp4, q_tile 64),
                          12/13/14 = split-K kernel on a ring of 2/3/4 stages (fp4,
-                         q_tile 64); 0 = default */
+                         q_tile 64), 15 = split-K kernel on a 2-stage ring whose
+                         selection words arrive 4 K-steps at a time (fp4, q_tile 64);
+                         0 = default */
     uint32_t groups;  /* record groups = partial results per query (0 = default) */
 } pir_kernel_cfg;
 

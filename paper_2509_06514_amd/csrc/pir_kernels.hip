@@ -981,6 +981,223 @@ k_stage1_mfma_ks(const uint32_t* __restrict__ db, const uint32_t* __restrict__ s
     }
 }
 
+// Split-K kernel with wide selection reads: the database ring is that of
+// k_stage1_mfma_ks (2 stages of 16 blocks), while the selection words move
+// in stages of 4 K-steps, 256 contiguous bytes per query row (two whole
+// 128-byte lines instead of half a line per row and step), double-buffered.
+// A selection stage holds rows 4i .. 4i+3 at i * kWsRowGroup (one 1 KiB
+// load, 64 bytes of padding after it), row r's 16-byte chunk c at
+// (r & 3) * 256 + 16 * (c ^ (r & 3)) within its group.
+constexpr uint32_t kWsRowGroup = 1024 + 64;
+constexpr uint32_t kWsStageSelBytes = 16 * kWsRowGroup;
+constexpr uint32_t kWsLdsBytes = 2 * kStageDbBytes + 2 * kWsStageSelBytes;
+
+// Largest selection pitch (32-bit words) for which the wide loads' lane
+// offsets, up to three rows plus 256 bytes, fit in 32 bits.
+constexpr uint64_t kWsMaxStrideWords = ((1ull << 32) - 256) / 12;
+
+// Operand reads of one K-step for k_stage1_mfma_ksw: the database chunks as
+// in lds_read_ks, and both sub-steps' selection words of each row tile at
+// `a` + rt * 4 * kWsRowGroup.
+__device__ __forceinline__ void lds_read_ksw(uint32_t b, uint32_t a, u32x4 (&bw)[4], u32x2 (&aw)[4]) {
+    asm volatile(
+        "ds_read_b128 %0, %8\n\t"
+        "ds_read_b128 %1, %8 offset:256\n\t"
+        "ds_read_b128 %2, %8 offset:1024\n\t"
+        "ds_read_b128 %3, %8 offset:1280\n\t"
+        "ds_read_b64 %4, %9\n\t"
+        "ds_read_b64 %5, %9 offset:4352\n\t"
+        "ds_read_b64 %6, %9 offset:8704\n\t"
+        "ds_read_b64 %7, %9 offset:13056\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(bw[0]), "=&v"(bw[1]), "=&v"(bw[2]), "=&v"(bw[3]), "=&v"(aw[0]), "=&v"(aw[1]),
+          "=&v"(aw[2]), "=&v"(aw[3])
+        : "v"(b), "v"(a));
+}
+static_assert(4 * kWsRowGroup == 4352, "row-tile offset in lds_read_ksw");
+
+// The contraction, the database loads and the K-half fold are those of
+// k_stage1_mfma_ks<2>.  Selection stage m (K-steps 4m .. 4m+3) is loaded
+// during the steps of stage m - 1, one 1 KiB load per wave and step (load
+// 4s + w in step s by wave w), so every step still issues a fixed amount.
+// Each step waits for all of its wave's earlier loads and then meets the
+// others at a barrier, as in the 2-stage ring.
+__global__ void __launch_bounds__(kThreads)
+k_stage1_mfma_ksw(const uint32_t* __restrict__ db, const uint32_t* __restrict__ sel,
+                  uint8_t* __restrict__ partials, Stage1Params p) {
+    constexpr int MT = 4, NT = 8, QT = 64;
+    extern __shared__ __attribute__((aligned(16))) uint8_t pir_ring[];
+    uint8_t* const ring_db = pir_ring;
+    uint8_t* const ring_sel = pir_ring + 2 * kStageDbBytes;
+
+    uint32_t group, ct, qt;
+    if (!decode_block(p.groups, p.n_ct, p.n_qt, group, ct, qt)) return;
+
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t c = wave & 1, h = wave >> 1;
+    const uint32_t j = lane & 15, g = lane >> 4;
+    const uint32_t q0 = qt * QT;
+    const uint64_t block_words = 8ull * p.R;
+    const uint64_t b_begin = (uint64_t)group * p.units_per_group;
+    const uint64_t b_end = (b_begin + p.units_per_group < p.n_units) ? b_begin + p.units_per_group : p.n_units;
+    const uint32_t nsteps = (uint32_t)((b_end - b_begin) / kMfmaBlocksPerStep);
+
+    // database: wave w loads blocks w, w+4, w+8, w+12 of a step (lane l:
+    // words 4l..4l+3 of the tile)
+    const uint8_t* db_tile = reinterpret_cast<const uint8_t*>(db + ct * 256);
+    const uint32_t db_off = 16 * lane;
+    auto issue_db = [&](uint32_t k, uint32_t slot) {
+        uint8_t* dst = ring_db + slot * kStageDbBytes;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t b = 4 * i + wave;
+            const uint8_t* base =
+                uniform_ptr(db_tile + (b_begin + (uint64_t)k * kMfmaBlocksPerStep + b) * block_words * 4);
+            // database chunks are read once: nontemporal (cache policy NT = 2)
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint32_t*>(base + db_off), dst + b * 1024, 16,
+                                             0, 2);
+        }
+    };
+
+    // selection load 4s + w covers rows r0 = q0 + 4(4s + w) .. +3; lane l
+    // reads row r0 + l/16, chunk (l & 15) ^ (l >> 4).  A row past q_total
+    // reads the first row of its load (or row q0), a valid row never
+    // written out.
+    const uint32_t ch = (lane & 15) ^ (lane >> 4);
+    const uint8_t* sel_row[4];
+    uint32_t sel_off[4];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+        uint32_t r0 = q0 + 4 * (4 * st + wave);
+        const bool any = r0 < p.q_total;
+        if (!any) r0 = q0;
+        const uint32_t rl = (any && r0 + lane / 16 < p.q_total) ? lane / 16 : 0;
+        sel_row[st] = reinterpret_cast<const uint8_t*>(sel + (uint64_t)r0 * p.stride_words + b_begin);
+        sel_off[st] = rl * (uint32_t)(p.stride_words * 4) + 16 * ch;
+    }
+    // a chunk of a K-step past the group's last full step re-reads the same
+    // position of the stage's first step (valid, never used)
+    auto issue_sel = [&](uint32_t m, int st) {
+        uint32_t off = sel_off[st];
+        if (4 * m + 3 >= nsteps && 4 * m + (ch >> 2) >= nsteps) off -= 16 * (ch & ~3u);
+        __builtin_amdgcn_global_load_lds(
+            reinterpret_cast<const uint32_t*>(uniform_ptr(sel_row[st] + (uint64_t)m * 256) + off),
+            ring_sel + (m & 1) * kWsStageSelBytes + (4 * st + wave) * kWsRowGroup, 16, 0, 0);
+    };
+
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int rt = 0; rt < MT; ++rt)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[rt][t] = f32x4{0, 0, 0, 0};
+
+    // bw[2*sl + half]: sub-step 2h + sl, columns 128c + 64*half + 4j .. +3;
+    // aw[rt][sl]: selection word of row 16rt + j for that sub-step
+    auto mma = [&](const u32x4 bw[4], const u32x2 aw[MT]) {
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+            i32x8 bx[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) bx[t] = spread_fp4_b(bw[2 * sl + (t >> 2)][t & 3]);
+#pragma unroll
+            for (int rt = 0; rt < MT; ++rt) {
+                const i32x8 ax = spread_fp4_a(aw[rt][sl]);
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[rt][t] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(ax, bx[t], acc[rt][t], 4, 4, 0,
+                                                                                 127, 0, 127);
+            }
+        }
+    };
+    const uint32_t rd_db =
+        (uint32_t)(uintptr_t)(ring_db + (4 * g + 2 * h) * 1024 + (128 * c + 4 * j) * 4);
+    // row 16rt + j, word 16s + 4g + 2h (chunk 4s + g) of stage buffer m & 1
+    const uint32_t rd_sel = (uint32_t)(uintptr_t)(ring_sel + (j >> 2) * kWsRowGroup + (j & 3) * 256 +
+                                                  16 * (g ^ (j & 3)) + 8 * h);
+
+    if (nsteps > 0) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) issue_sel(0, st);
+        issue_db(0, 0);
+    }
+    for (uint32_t m = 0; 4 * m < nsteps; ++m) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            const uint32_t k = 4 * m + st;
+            if (k >= nsteps) break;
+            wait_vmcnt<0>();  // this wave's loads of step k (and of stage m) have landed
+            wg_barrier();     // ... and everyone's; step k - 1's stages have been read
+            if (k + 1 < nsteps) issue_db(k + 1, (k + 1) & 1);
+            if (4 * (m + 1) < nsteps) issue_sel(m + 1, st);
+            u32x4 bw[4];
+            u32x2 aw[MT];
+            lds_read_ksw(rd_db + (k & 1) * kStageDbBytes, rd_sel + (m & 1) * kWsStageSelBytes + 64 * st, bw, aw);
+            mma(bw, aw);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+
+    // ragged tail (fewer than 16 blocks) straight from memory
+    const uint64_t kb = b_begin + (uint64_t)nsteps * kMfmaBlocksPerStep;
+    if (kb < b_end) {
+        const u32x4* dl = reinterpret_cast<const u32x4*>(db + ct * 256 + 128 * c + 4 * j);
+        u32x4 bw[4];
+        u32x2 aw[MT];
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+            const uint64_t blk = kb + 4 * g + 2 * h + sl;
+            const bool ok = blk < b_end;
+            bw[2 * sl] = ok ? dl[blk * (block_words / 4)] : u32x4{0, 0, 0, 0};
+            bw[2 * sl + 1] = ok ? dl[blk * (block_words / 4) + 16] : u32x4{0, 0, 0, 0};
+#pragma unroll
+            for (int rt = 0; rt < MT; ++rt) {
+                const uint32_t q = q0 + 16 * rt + j;
+                aw[rt][sl] = (ok && q < p.q_total) ? sel[(uint64_t)q * p.stride_words + blk] : 0u;
+            }
+        }
+        mma(bw, aw);
+    }
+
+    // answer bits: lane holds columns 128c + 64*half + 4j + t' of rows
+    // 16rt + 4g + r; bit 8r + 4*half + t' of par[rt]
+    uint32_t par[MT];
+#pragma unroll
+    for (int rt = 0; rt < MT; ++rt) {
+        par[rt] = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) par[rt] |= (((uint32_t)acc[rt][t][r]) & 1u) << (8 * r + t);
+    }
+    // fold the K halves through LDS (every load has landed and, after this
+    // barrier, every wave has read its last stage)
+    __syncthreads();
+    u32x4* fold = reinterpret_cast<u32x4*>(pir_ring) + c * 64 + lane;
+    if (h == 1) *fold = u32x4{par[0], par[1], par[2], par[3]};
+    __syncthreads();  // the fold writes are complete and visible
+    if (h == 1) return;
+    const u32x4 o = *fold;
+    par[0] ^= o[0];
+    par[1] ^= o[1];
+    par[2] ^= o[2];
+    par[3] ^= o[3];
+#pragma unroll
+    for (int rt = 0; rt < MT; ++rt) {
+        const uint32_t other = (uint32_t)__shfl_xor((int)par[rt], 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t q = q0 + 16 * rt + 4 * g + r;
+            const uint32_t mine = par[rt] >> (8 * r), theirs = other >> (8 * r);
+            if ((j & 1) == 0 && q < p.q_total) {
+                uint8_t* dst = partials + ((uint64_t)group * p.q_total + q) * p.rpad + ct * 32 + 16 * c + j / 2;
+                dst[0] = (uint8_t)((mine & 0xF) | ((theirs & 0xF) << 4));
+                dst[8] = (uint8_t)(((mine >> 4) & 0xF) | (theirs & 0xF0));
+            }
+        }
+    }
+}
+
 // Stage 2: out[q][m] = XOR over groups of partials[g][q][m].  Each workgroup
 // owns `wpb` consecutive 32-bit words of the [q][rpad] result and splits the
 // groups over 256 / wpb slices, then folds the slices through LDS.
@@ -1157,6 +1374,8 @@ bool mfma_supported(uint32_t variant, const Geometry& g, uint32_t qt, uint32_t u
     if (unroll == 7) return variant == PIR_VARIANT_MFMA_F4 && qt == 64;
     // 12, 13, 14 = split-K kernel on a ring of 2, 3, 4 stages (fp4, 64-query tiles)
     if (unroll >= 12 && unroll <= 14) return variant == PIR_VARIANT_MFMA_F4 && qt == 64;
+    // 15 = split-K kernel, 2-stage ring, selection words in 4-step stages (fp4, 64-query tiles)
+    if (unroll == 15) return variant == PIR_VARIANT_MFMA_F4 && qt == 64;
     if (unroll != 1 && unroll != 2 && unroll != 3 && unroll != 4 && unroll != 6) return false;
     return qt == 16 || qt == 32 || qt == 64;
 }
@@ -1183,6 +1402,15 @@ static hipError_t launch_ks(dim3 grid, hipStream_t s, const uint32_t* db, const 
     const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ks<S>), (int)bytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_stage1_mfma_ks<S>), grid, dim3(kThreads), bytes, s, db, sel, partials, p);
+    return hipGetLastError();
+}
+
+static hipError_t launch_ksw(dim3 grid, hipStream_t s, const uint32_t* db, const uint32_t* sel, uint8_t* partials,
+                             const Stage1Params& p) {
+    if (p.stride_words > kWsMaxStrideWords) return launch_ks<2>(grid, s, db, sel, partials, p);
+    const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksw), (int)kWsLdsBytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_stage1_mfma_ksw, grid, dim3(kThreads), kWsLdsBytes, s, db, sel, partials, p);
     return hipGetLastError();
 }
 
@@ -1223,6 +1451,9 @@ static hipError_t launch_mfma_t(const Geometry& g, const Plan& pl, const void* d
                 if (pl.unroll == 13) return launch_ks<3>(grid, s, d, sel, partials, p);
                 return launch_ks<4>(grid, s, d, sel, partials, p);
             }
+            return hipErrorInvalidValue;
+        case 15:
+            if constexpr (MT == 4 && F4) return launch_ksw(grid, s, d, sel, partials, p);
             return hipErrorInvalidValue;
         default:
             hipLaunchKernelGGL((k_stage1_mfma<MT, F4>), grid, dim3(kThreads), 0, s, d, sel, partials, p);

@@ -372,10 +372,11 @@ int Ctx::plan_for(const Db& db, uint32_t q, const pir_kernel_cfg* cfg, Plan& p) 
             base.groups = it->second.groups;
         } else if (q >= 8 && mfma_supported(PIR_VARIANT_MFMA_F4, db.geo, 16, 4)) {
             // untuned: from 8 queries up the fp4 matrix cores (the split-K
-            // kernel for 64-query tiles), as the tuner picks on MI355X
+            // kernel with wide selection reads for 64-query tiles), as the
+            // tuner picks on MI355X
             base.variant = PIR_VARIANT_MFMA_F4;
             base.qt = q <= 16 ? 16 : (q <= 32 ? 32 : 64);
-            base.unroll = base.qt == 64 ? 12 : 4;
+            base.unroll = base.qt == 64 ? 15 : 4;
         } else {
             base.variant = PIR_VARIANT_VALU;
         }
@@ -835,7 +836,7 @@ int pir_tune(pir_db* d, uint32_t q, pir_kernel_cfg* out) {
     // 16-query tile with idle rows is still worth timing
     for (uint32_t v : {PIR_VARIANT_MFMA_I8, PIR_VARIANT_MFMA_F4})
         for (uint32_t qt : {16u, 32u, 64u})
-            for (uint32_t u : {1u, 2u, 3u, 4u, 6u, 7u, 12u, 13u, 14u})
+            for (uint32_t u : {1u, 2u, 3u, 4u, 6u, 7u, 12u, 13u, 14u, 15u})
                 if (q >= 8 && qt <= std::max<uint32_t>(qmax_tile, 16) && mfma_supported(v, g, qt, u))
                     cands.push_back({v, qt, u, 0});
     // grid variants of each: the default record-group count, half and double

@@ -72,6 +72,7 @@ def test_c4_variants_agree(c4, q):
             assert np.array_equal(ref[i], want)
     for cfg in (pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 7, 0),
                 pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 12, 0),
+                pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 15, 0),
                 pir.KernelCfg(pir.PIR_VARIANT_MFMA_I8, 64, 6, 0),
                 pir.KernelCfg(pir.PIR_VARIANT_MFMA_I8, 32, 1, 0),
                 pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 32, 3, 0),

@@ -205,8 +205,9 @@ def test_mfma_variants(ctx, variant, n, r):
     for q in qs:
         d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
         for qt in (16, 32, 64):
-            # registers, LDS rings of 2/3/4/6 stages, shared spread, split K on 2/3/4 stages
-            for unroll in (1, 2, 3, 4, 6, 7, 12, 13, 14):
+            # registers, LDS rings of 2/3/4/6 stages, shared spread, split K on 2/3/4
+            # stages, split K with selection words 4 K-steps at a time
+            for unroll in (1, 2, 3, 4, 6, 7, 12, 13, 14, 15):
                 if unroll >= 7 and not (variant == pir.PIR_VARIANT_MFMA_F4 and qt == 64):
                     continue
                 for groups in (0, 3, 1):
@@ -236,7 +237,7 @@ def test_mfma_counts_exact_on_large_group(ctx, variant):
     want3 = oracle.dpxor(dbh, rnd[0])
     cfgs = [(16, 1), (16, 3), (16, 6)]
     if variant == pir.PIR_VARIANT_MFMA_F4:
-        cfgs.append((64, 13))  # split K: each half's counts and their sum stay exact
+        cfgs += [(64, 13), (64, 15)]  # split K: each half's counts and their sum stay exact
     for qt, unroll in cfgs:
         d_out.fill_(0)
         db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride, cfg=pir.KernelCfg(variant, qt, unroll, 1))
