@@ -368,7 +368,7 @@ def fp_bench(ctx, args, torch, pir):
     q = args.fp_queries
     D = (synth.stream_bytes(synth.S_DB + 9, n * L).reshape(n, L) % p).astype(np.uint8)
     db = ctx.load_fp_db(D, p)
-    stride = db.min_v_stride
+    stride = db.v_stride  # recommended pitch: an odd multiple of 128 bytes
     rows = (synth.stream_bytes(synth.S_SEL + 9, q * stride).reshape(q, stride) & 127).astype(np.uint8)
     # rows 0 and 1: additive shares of the unit vector at index i
     i = n // 3
@@ -378,7 +378,7 @@ def fp_bench(ctx, args, torch, pir):
     rows[:, n:] = 0
     d_v = torch.from_numpy(rows).to("cuda:0")
     d_out = torch.empty((q, L), dtype=torch.uint8, device="cuda:0")
-    out = {"n_records": n, "record_elems": L, "p": p, "q": q}
+    out = {"n_records": n, "record_elems": L, "p": p, "q": q, "v_stride": stride}
     for qq in (q, 1):
         def step():
             db.inner_async(d_v, qq, d_out)
@@ -391,7 +391,7 @@ def fp_bench(ctx, args, torch, pir):
         t = ctx.timing_read(reset=True)
         ctx.timing(False)
         s1 = t["fp_ms"] / max(1, t["fp_launches"])
-        alg = n * L + qq * stride + qq * L
+        alg = n * L + qq * db.min_v_stride + qq * L
         ach = alg / (s1 / 1e3) / 1e9
         rec = {"ms_per_pass": wall / args.steps * 1e3, "queries_per_s": qq * args.steps / wall,
                "latency_ms": {"p50": percentile(per, 0.5), "p99": percentile(per, 0.99)},

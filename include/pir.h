@@ -420,6 +420,13 @@ int pir_fp_db_read(pir_fpdb* db, uint64_t first, uint64_t count, void* out_eleme
  * NULL).  Bytes of a row past N are read and meet zero records. */
 uint64_t pir_fp_min_v_stride(const pir_fpdb* db);
 
+/* Recommended query row pitch for the device call: the smallest odd multiple
+ * of 128 bytes >= pir_fp_min_v_stride (0 for NULL).  The scan reads 64 rows
+ * at once; at a power-of-two pitch of many MiB they crowd the same HBM
+ * channels (2^24 records x 32 elements, Q = 64: 0.27 ms at pitch 2^24, 0.25
+ * ms at 2^24 + 128).  The synchronous call stages rows at this pitch. */
+uint64_t pir_fp_v_stride(const pir_fpdb* db);
+
 /*
  * Q queries on device buffers, asynchronous on hip_stream.  d_v: q rows of
  * v_stride bytes (a multiple of 16, >= pir_fp_min_v_stride), base 16-byte

@@ -326,6 +326,7 @@ class FpDatabase:
         self._h = handle
         self.n_records, self.record_elems, self.p = n_records, record_elems, p
         self.min_v_stride = lib().pir_fp_min_v_stride(handle)
+        self.v_stride = lib().pir_fp_v_stride(handle)  # recommended row pitch (odd multiple of 128)
 
     @property
     def handle(self):

@@ -113,6 +113,7 @@ SIGNATURES = {
     "pir_fp_db_free": (_I, [_P]),
     "pir_fp_db_read": (_I, [_P, _U64, _U64, _P]),
     "pir_fp_min_v_stride": (_U64, [_P]),
+    "pir_fp_v_stride": (_U64, [_P]),
     "pir_fp_inner_async": (_I, [_P, _P, _U64, _U32, _P, _P]),
     "pir_fp_inner": (_I, [_P, _P, _U64, _U32, _P]),
     "pir_host_alloc": (_P, [ctypes.c_size_t]),

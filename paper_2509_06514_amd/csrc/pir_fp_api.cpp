@@ -173,6 +173,20 @@ uint64_t pir_fp_min_v_stride(const pir_fpdb* d) {
     return reinterpret_cast<const FpDb*>(d)->tiles * 64;
 }
 
+// Query-row pitch for the scan: the smallest odd multiple of 128 bytes that
+// holds a row.  A wave's loads touch 64 rows at once; at a power-of-two pitch
+// of many MiB those rows share every low address bit and so crowd the same
+// HBM channels and banks, which an odd multiple of 128 avoids.
+static uint64_t fp_pitch(uint64_t min_bytes) {
+    const uint64_t lines = (min_bytes + 127) / 128;
+    return 128 * (lines | 1);
+}
+
+uint64_t pir_fp_v_stride(const pir_fpdb* d) {
+    if (!d) return 0;
+    return fp_pitch(reinterpret_cast<const FpDb*>(d)->tiles * 64);
+}
+
 int pir_fp_db_read(pir_fpdb* d, uint64_t first, uint64_t count, void* out_elements) {
     clear_error();
     if (!d || !out_elements) return fail(PIR_E_INVAL, "pir_fp_db_read: NULL argument");
@@ -239,7 +253,7 @@ int pir_fp_inner(pir_fpdb* d, const uint8_t* v, uint64_t v_stride, uint32_t q, u
         Exec* e;
         ~Releaser() { c->release(e); }
     } rel{ctx, ex};
-    const uint64_t dstride = (db->tiles * 64 + 255) / 256 * 256;
+    const uint64_t dstride = fp_pitch(db->tiles * 64);
     const size_t v_bytes = (size_t)dstride * q, out_bytes = (size_t)q * db->L;
     hipError_t e;
     if ((e = ex->h_sel.ensure(v_bytes)) != hipSuccess) return hip_fail(e, "pinned query staging");

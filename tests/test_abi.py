@@ -44,6 +44,8 @@ def test_null_arguments_rejected_without_device_work():
     assert lib.pir_serve_create(None, None, ctypes.byref(out)) == _native.PIR_E_INVAL
     assert lib.pir_serve_submit(None, 0, None, None, None) == _native.PIR_E_INVAL
     assert lib.pir_db_min_sel_stride(None) == 0
+    assert lib.pir_fp_min_v_stride(None) == 0
+    assert lib.pir_fp_v_stride(None) == 0
     assert lib.pir_host_alloc(0) is None
 
 
@@ -54,7 +56,14 @@ def test_sel_stride_helper():
     assert pir.sel_stride_for(1 << 28, align=4) == (1 << 28) // 8
 
 
-@pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES") is None and os.path.exists("/dev/kfd"),
+def _gpu_may_be_present():
+    hvd = os.environ.get("HIP_VISIBLE_DEVICES")
+    if hvd is not None and hvd.strip() in ("", "-1"):
+        return False  # every device hidden
+    return os.path.exists("/dev/kfd")
+
+
+@pytest.mark.skipif(_gpu_may_be_present(),
                     reason="a GPU may be present; the no-device path is checked where there is none")
 def test_no_device_fails_loudly():
     lib = pir.lib()

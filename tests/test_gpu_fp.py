@@ -132,8 +132,31 @@ def test_rejects_bad_arguments(ctx):
     v = torch.zeros((2, 128), dtype=torch.uint8, device="cuda:0")
     out = torch.zeros((2, 4), dtype=torch.uint8, device="cuda:0")
     assert db.min_v_stride == 128
+    assert db.v_stride == 128
     assert lib.pir_fp_inner_async(db.handle, v.data_ptr(), 112, 2, out.data_ptr(), None) == E  # < 128
     assert lib.pir_fp_inner_async(db.handle, v.data_ptr(), 136, 1, out.data_ptr(), None) == E  # not x16
     assert lib.pir_fp_inner_async(db.handle, v.data_ptr() + 8, 128, 1, out.data_ptr(), None) == E
     assert lib.pir_fp_inner_async(db.handle, v.data_ptr(), 128, 0, out.data_ptr(), None) == E
+    db.free()
+
+
+@pytest.mark.parametrize("n", [64, 4097, 65536, 100003])
+def test_recommended_pitch(ctx, n):
+    # the recommended row pitch is the smallest odd multiple of 128 bytes that
+    # holds a row, and the scan at that pitch gives the oracle's rows
+    L, p, q = 16, 101, 17
+    D = _db(n, L, p, synth.S_DB + 300 + n)
+    db = ctx.load_fp_db(D, p)
+    vs = db.v_stride
+    assert vs >= db.min_v_stride and vs % 128 == 0 and (vs // 128) % 2 == 1
+    assert vs - 256 < db.min_v_stride
+    rows = _queries(q, vs, synth.S_SEL + 300 + n)
+    rows[:, n:] = 0
+    d_v = torch.from_numpy(rows).to("cuda:0")
+    d_out = torch.full((q, L), 0xEE, dtype=torch.uint8, device="cuda:0")
+    db.inner_async(d_v, q, d_out, v_stride=vs)
+    torch.cuda.synchronize()
+    want = np.stack([oracle.fp_inner(D, rows[i, :n], p) for i in range(q)])
+    assert np.array_equal(d_out.cpu().numpy(), want)
+    assert np.array_equal(db.inner(rows[:, :n]), want)  # synchronous call, staged at the same pitch
     db.free()
