@@ -1199,8 +1199,9 @@ k_stage1_mfma_ksw(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
 }
 
 // Stage 2: out[q][m] = XOR over groups of partials[g][q][m].  Each workgroup
-// owns `wpb` consecutive 32-bit words of the [q][rpad] result and splits the
-// groups over 256 / wpb slices, then folds the slices through LDS.
+// owns `wpb` consecutive 32-bit words of the [q][rpad] result (wpb a power of
+// two) and splits the groups over 256 / wpb slices, then folds the slices
+// through LDS.
 __global__ void __launch_bounds__(kThreads)
 k_stage2(const uint32_t* __restrict__ partials, uint8_t* __restrict__ out, uint32_t groups,
          uint32_t words, uint32_t wpb, uint32_t rpad, uint32_t R) {
@@ -1210,21 +1211,30 @@ k_stage2(const uint32_t* __restrict__ partials, uint8_t* __restrict__ out, uint3
     const uint32_t w = blockIdx.x * wpb + wl;
     uint32_t acc = 0;
     if (w < words && sl < nsl) {
-        uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        // 16 independent loads in flight per thread: the walk over the
+        // groups is latency-bound (few workgroups), not bandwidth-bound
+        constexpr uint32_t U = 16;
+        uint32_t a[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) a[u] = 0;
         uint32_t g = sl;
-        for (; g + 3 * nsl < groups; g += 4 * nsl) {
-            a0 ^= partials[(uint64_t)g * words + w];
-            a1 ^= partials[(uint64_t)(g + nsl) * words + w];
-            a2 ^= partials[(uint64_t)(g + 2 * nsl) * words + w];
-            a3 ^= partials[(uint64_t)(g + 3 * nsl) * words + w];
+        for (; g + (U - 1) * nsl < groups; g += U * nsl) {
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) a[u] ^= partials[(uint64_t)(g + u * nsl) * words + w];
         }
-        for (; g < groups; g += nsl) a0 ^= partials[(uint64_t)g * words + w];
-        acc = a0 ^ a1 ^ a2 ^ a3;
+        for (; g < groups; g += nsl) a[0] ^= partials[(uint64_t)g * words + w];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) acc ^= a[u];
     }
+    // fold the slices pairwise (nsl is a power of two)
     red[threadIdx.x] = acc;
+    for (uint32_t half = nsl / 2; half > 0; half /= 2) {
+        __syncthreads();
+        if (sl < half) red[threadIdx.x] ^= red[threadIdx.x + half * wpb];
+    }
     __syncthreads();
     if (sl == 0 && w < words) {
-        for (uint32_t s = 1; s < nsl; ++s) acc ^= red[s * wpb + wl];
+        acc = red[wl];
         const uint32_t q = (4 * w) / rpad, m0 = (4 * w) - q * rpad;
         for (uint32_t b = 0; b < 4; ++b) {
             const uint32_t m = m0 + b;
@@ -1338,7 +1348,10 @@ hipError_t launch_stage1_valu(const Geometry& g, const Plan& p, const void* db, 
 hipError_t launch_stage2(const Geometry& g, uint32_t groups, uint32_t q, const uint8_t* partials,
                          uint8_t* out, hipStream_t s) {
     const uint32_t words = q * (g.rpad / 4);
-    const uint32_t wpb = words < 16 ? words : 16;
+    // at least ~128 workgroups where the result allows: the walk over the
+    // groups is latency-bound, and narrower word tiles give more workgroups
+    // and fewer groups per thread (4 words = 16 contiguous bytes per group)
+    const uint32_t wpb = words >= 16 * 128 ? 16 : (words >= 8 * 128 ? 8 : 4);
     const uint32_t grid = (words + wpb - 1) / wpb;
     hipLaunchKernelGGL(k_stage2, dim3(grid), dim3(kThreads), 0, s, (const uint32_t*)partials, out,
                        groups, words, wpb, g.rpad, g.R);
