@@ -79,8 +79,16 @@ k_fp_finish(const uint32_t* __restrict__ tmp, uint32_t slices, uint64_t outputs,
             uint8_t* __restrict__ out) {
     const uint64_t o = (uint64_t)blockIdx.x * kFpThreads + threadIdx.x;
     if (o >= outputs) return;
-    uint32_t s = 0;  // < groups * 126 < 2^32
-    for (uint32_t k = 0; k < slices; ++k) s += tmp[(uint64_t)k * outputs + o];
+    // 8 independent loads in flight: few workgroups, so the walk over the
+    // slices is latency-bound
+    uint32_t a[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // sums < groups * 126 < 2^32
+    uint32_t k = 0;
+    for (; k + 8 <= slices; k += 8) {
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) a[u] += tmp[(uint64_t)(k + u) * outputs + o];
+    }
+    for (; k < slices; ++k) a[0] += tmp[(uint64_t)k * outputs + o];
+    const uint32_t s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     out[o] = (uint8_t)mod_p(s, p, magic);
 }
 
