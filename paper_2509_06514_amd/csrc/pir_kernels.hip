@@ -1017,11 +1017,11 @@ __device__ __forceinline__ void lds_read_ksw(uint32_t b, uint32_t a, u32x4 (&bw)
 static_assert(4 * kWsRowGroup == 4352, "row-tile offset in lds_read_ksw");
 
 // The contraction, the database loads and the K-half fold are those of
-// k_stage1_mfma_ks<2>.  Selection stage m (K-steps 4m .. 4m+3) is loaded
-// during the steps of stage m - 1, one 1 KiB load per wave and step (load
-// 4s + w in step s by wave w), so every step still issues a fixed amount.
-// Each step waits for all of its wave's earlier loads and then meets the
-// others at a barrier, as in the 2-stage ring.
+// k_stage1_mfma_ks<2>.  Selection stage 0 is loaded before the first step
+// and stage m + 1 during the steps of stage m, one 1 KiB load per wave and
+// step (load 4s + w in step s by wave w); the steps of the last stage load
+// no selection words.  Each step waits for all of its wave's earlier loads
+// and then meets the others at a barrier, as in the 2-stage ring.
 __global__ void __launch_bounds__(kThreads)
 k_stage1_mfma_ksw(const uint32_t* __restrict__ db, const uint32_t* __restrict__ sel,
                   uint8_t* __restrict__ partials, Stage1Params p) {
