@@ -24,14 +24,14 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit lane ops/s: 256 CUs x 64 lan
 MFMA_PEAK_TFLOPS = {"int8": 5000.0, "fp4": 10100.0}  # dense, vendor figures
 
 CONFIGS = {
-    # name: (n_records, record_bytes, q)
-    "c4": (1 << 28, 32, 64),
-    "c4q16": (1 << 28, 32, 16),
-    "c4q512": (1 << 28, 32, 512),
-    "c2": (1 << 25, 32, 1),
-    "c3q8": (1 << 23, 256, 8),
-    "c3q64": (1 << 23, 256, 64),
-    "c3q256": (1 << 23, 256, 256),
+    # name: (n_records, record_bytes, q) -- n<log2 N>r<R>q<Q>
+    "n28r32q64": (1 << 28, 32, 64),
+    "n28r32q16": (1 << 28, 32, 16),
+    "n28r32q512": (1 << 28, 32, 512),
+    "n25r32q1": (1 << 25, 32, 1),
+    "n23r256q8": (1 << 23, 256, 8),
+    "n23r256q64": (1 << 23, 256, 64),
+    "n23r256q256": (1 << 23, 256, 256),
 }
 
 VARIANT_DTYPE = {1: "u32", 2: "int8", 3: "fp4"}
@@ -65,10 +65,10 @@ def kernel_name(cfg, r):
     return f"k_stage1_mfma<{mt}, {f4}>"
 
 
-def load_traffic(name, q, cfg, r):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they are for this kernel
-    (same source hash, same kernel instance); else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
+def load_traffic(n, r, q, cfg):
+    """HBM bytes per launch from committed rocprofv3 counter runs on this database (2^k records
+    of r bytes), if they are for this kernel (same source hash, same kernel instance); else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_dpxor_n{n.bit_length() - 1}r{r}.json")
     try:
         with open(path) as f:
             t = json.load(f)
@@ -568,7 +568,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c4", choices=sorted(CONFIGS))
+    ap.add_argument("--config", default="n28r32q64", choices=sorted(CONFIGS))
     ap.add_argument("--no-tune", action="store_true", help="use the default kernel plan")
     ap.add_argument("--variants", action="store_true",
                     help="also time the best plan of each kernel family (VALU, int8 MFMA, fp4 MFMA) for Q")
@@ -701,7 +701,7 @@ def main():
             "db_gbs_scanned": n * r / (ms1 / 1e3) / 1e9,
             "latency_ms": {"p50": percentile(per_1, 0.5), "p99": percentile(per_1, 0.99)},
             "cfg": cfg_1.as_dict(),
-            "roofline": roofline_for(cfg_1.variant, n, r, 1, s1_avg, load_traffic(args.config, 1, cfg_1, r)),
+            "roofline": roofline_for(cfg_1.variant, n, r, 1, s1_avg, load_traffic(n, r, 1, cfg_1)),
         }
         log(f"Q=1: {ms1:.3f} ms/query, {single['db_gbs_scanned']:.0f} GB/s scanned, stage1 avg {s1_avg:.3f} ms")
 
@@ -729,7 +729,7 @@ def main():
         "db_gbs_scanned": n * r / (ms_step / 1e3) / 1e9,
         "latency_ms": {"p50": percentile(per_q, 0.5), "p99": percentile(per_q, 0.99)},
         "stage_ms": {"stage1_avg": s1q, "stage2_avg": tq["stage2_ms"] / max(1, tq["stage2_launches"])},
-        "roofline": roofline_for(cfg_q.variant, n, r, q, s1q, load_traffic(args.config, q, cfg_q, r)),
+        "roofline": roofline_for(cfg_q.variant, n, r, q, s1q, load_traffic(n, r, q, cfg_q)),
     }
     if single is not None:
         result["single_query"] = single

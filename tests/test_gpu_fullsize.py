@@ -36,7 +36,7 @@ def _run(db, d_sel, stride, q, cfg=None):
 
 
 @pytest.fixture(scope="module")
-def c4(ctx):
+def db_n28r32(ctx):
     # 2^28 records x 32 B = 8 GiB, the benchmark's database and selections
     n, r = 1 << 28, 32
     dbh = synth.database(n, r, seed=synth.S_DB + 3)
@@ -51,8 +51,8 @@ def c4(ctx):
 
 
 @pytest.mark.parametrize("q", [1, 16, 64, 512])
-def test_c4_tuned_plan_matches_oracle_rows(c4, q):
-    dbh, db, sel, d_sel, stride, rows = c4
+def test_n28r32_tuned_plan_matches_oracle_rows(db_n28r32, q):
+    dbh, db, sel, d_sel, stride, rows = db_n28r32
     cfg = db.tune(q)  # what bench.py does before timing
     assert db.get_cfg(q).as_dict() == cfg.as_dict()
     got = _run(db, d_sel, stride, q)  # default path = the tuned plan
@@ -63,9 +63,9 @@ def test_c4_tuned_plan_matches_oracle_rows(c4, q):
 
 
 @pytest.mark.parametrize("q", [64, 512])
-def test_c4_variants_agree(c4, q):
+def test_n28r32_variants_agree(db_n28r32, q):
     # bitwise select-XOR, int8 matrix cores and fp4 matrix cores: identical rows
-    dbh, db, sel, d_sel, stride, rows = c4
+    dbh, db, sel, d_sel, stride, rows = db_n28r32
     ref = _run(db, d_sel, stride, q, pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 4, 0))
     for i, want in rows.items():
         if i < q:
@@ -81,9 +81,9 @@ def test_c4_variants_agree(c4, q):
         assert np.array_equal(got, ref), cfg
 
 
-def test_c4_two_server_identity(c4):
+def test_n28r32_two_server_identity(db_n28r32):
     # for random b and b XOR e_i (16 random i): ans(b) XOR ans(b XOR e_i) = D[i]
-    dbh, db, sel, d_sel, stride, rows = c4
+    dbh, db, sel, d_sel, stride, rows = db_n28r32
     n = dbh.shape[0]
     idx = synth.indices(n, 16, seed=synth.S_IDX + 3)
     pair = np.empty((1 + len(idx), stride), np.uint8)
@@ -98,7 +98,7 @@ def test_c4_two_server_identity(c4):
         assert np.array_equal(ans[0] ^ ans[k + 1], dbh[i]), i
 
 
-def test_c2_single_query_full_compare(ctx):
+def test_n25r32_single_query_full_compare(ctx):
     # 2^25 records x 32 B (1 GiB): the single-query roofline configuration
     n, r = 1 << 25, 32
     dbh = synth.database(n, r, seed=synth.S_DB + 2)
@@ -112,7 +112,7 @@ def test_c2_single_query_full_compare(ctx):
     db.free()
 
 
-def test_c3_batched_rows(ctx):
+def test_n23r256_batched_rows(ctx):
     # 2^23 records x 256 B (2 GiB), Q in {8, 64, 256} in one pass each
     n, r = 1 << 23, 256
     dbh = synth.database(n, r, seed=synth.S_DB + 4)
