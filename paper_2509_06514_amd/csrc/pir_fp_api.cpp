@@ -261,10 +261,7 @@ int pir_fp_inner(pir_fpdb* d, const uint8_t* v, uint64_t v_stride, uint32_t q, u
     if ((e = ex->h_out.ensure(out_bytes)) != hipSuccess) return hip_fail(e, "pinned answer staging");
     if ((e = ex->d_out.ensure(out_bytes)) != hipSuccess) return hip_fail(e, "device answer buffer");
     uint8_t* hs = (uint8_t*)ex->h_sel.ptr;
-    for (uint32_t i = 0; i < q; ++i) {
-        memcpy(hs + (size_t)i * dstride, v + (size_t)i * v_stride, db->n);
-        memset(hs + (size_t)i * dstride + db->n, 0, dstride - db->n);
-    }
+    pack_rows(hs, v, q, v_stride, db->n, dstride);
     if ((e = hipMemcpyAsync(ex->d_sel.ptr, hs, v_bytes, hipMemcpyHostToDevice, ex->stream)) != hipSuccess)
         return hip_fail(e, "query upload");
     if ((rc = enqueue_fp(*db, (const uint8_t*)ex->d_sel.ptr, dstride, q, (uint8_t*)ex->d_out.ptr, ex->partials,

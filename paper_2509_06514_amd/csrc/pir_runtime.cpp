@@ -18,6 +18,7 @@
 #include <mutex>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -430,6 +431,41 @@ void Ctx::load_tune_cache() {
     }
 }
 
+void pack_rows(uint8_t* dst, const uint8_t* src, uint32_t nr, uint64_t src_stride, uint64_t row_bytes,
+               uint64_t dstride) {
+    const uint64_t total = (uint64_t)nr * dstride;
+    const unsigned hw = std::thread::hardware_concurrency();
+    const unsigned T = total < (8ull << 20) ? 1u : std::min(8u, std::max(1u, hw));
+    // thread t packs bytes [total * t / T, total * (t + 1) / T) of the output
+    auto work = [=](unsigned t) {
+        const uint64_t hi = total * (t + 1) / T;
+        for (uint64_t off = total * t / T; off < hi;) {
+            const uint64_t r = off / dstride, c = off - r * dstride;
+            const uint64_t len = std::min(hi, (r + 1) * dstride) - off;
+            if (c < row_bytes) {
+                const uint64_t n = std::min(len, row_bytes - c);
+                memcpy(dst + off, src + r * src_stride + c, n);
+                if (len > n) memset(dst + off + n, 0, len - n);
+            } else {
+                memset(dst + off, 0, len);
+            }
+            off += len;
+        }
+    };
+    std::vector<std::thread> pool;
+    std::vector<unsigned> inline_parts;
+    for (unsigned t = 1; t < T; ++t) {
+        try {
+            pool.emplace_back(work, t);
+        } catch (...) {
+            inline_parts.push_back(t);
+        }
+    }
+    work(0);
+    for (unsigned t : inline_parts) work(t);
+    for (auto& th : pool) th.join();
+}
+
 }  // namespace pir
 
 using namespace pir;
@@ -485,7 +521,6 @@ int pir_ctx_destroy(pir_ctx* c) {
 // device copy.  Whole blocks are rewritten: a block only partly covered is
 // first read back (unsliced) so its other records survive.
 static int write_records(Db* db, uint64_t first, uint64_t count, const uint8_t* host) {
-    Ctx* ctx = db->ctx;
     const Geometry& g = db->geo;
     const uint32_t R = g.R;
     hipStream_t s = db->ctx_stream;
@@ -759,11 +794,7 @@ int pir_dpxor_batch(pir_db* d, const uint8_t* sel_bits, uint64_t sel_stride, uin
             if (c >= 2 && (e = hipEventSynchronize(ex->staged[half])) != hipSuccess)
                 return hip_fail(e, "selection staging");
             uint8_t* hs = (uint8_t*)ex->h_sel.ptr + (size_t)half * rows * dstride;
-            for (uint32_t i = 0; i < nr; ++i) {
-                uint8_t* row = hs + (size_t)i * dstride;
-                memcpy(row, sel_bits + (size_t)(r0 + i) * sel_stride, row_bytes);
-                memset(row + row_bytes, 0, dstride - row_bytes);
-            }
+            pack_rows(hs, sel_bits + (size_t)r0 * sel_stride, nr, sel_stride, row_bytes, dstride);
             if ((e = hipMemcpyAsync(ds + (size_t)r0 * dstride, hs, (size_t)nr * dstride, hipMemcpyHostToDevice,
                                     ex->stream)) != hipSuccess)
                 return hip_fail(e, "selection upload");
