@@ -431,25 +431,25 @@ void Ctx::load_tune_cache() {
     }
 }
 
-void pack_rows(uint8_t* dst, const uint8_t* src, uint32_t nr, uint64_t src_stride, uint64_t row_bytes,
-               uint64_t dstride) {
-    const uint64_t total = (uint64_t)nr * dstride;
+void pack_range(uint8_t* dst, const uint8_t* src, uint64_t src_stride, uint64_t row_bytes, uint64_t dstride,
+                uint64_t off, uint64_t len) {
     const unsigned hw = std::thread::hardware_concurrency();
-    const unsigned T = total < (8ull << 20) ? 1u : std::min(8u, std::max(1u, hw));
-    // thread t packs bytes [total * t / T, total * (t + 1) / T) of the output
+    const unsigned T = len < (8ull << 20) ? 1u : std::min(8u, std::max(1u, hw));
+    // thread t writes layout bytes [off + len * t / T, off + len * (t + 1) / T)
     auto work = [=](unsigned t) {
-        const uint64_t hi = total * (t + 1) / T;
-        for (uint64_t off = total * t / T; off < hi;) {
-            const uint64_t r = off / dstride, c = off - r * dstride;
-            const uint64_t len = std::min(hi, (r + 1) * dstride) - off;
+        const uint64_t hi = off + len * (t + 1) / T;
+        for (uint64_t o = off + len * t / T; o < hi;) {
+            const uint64_t r = o / dstride, c = o - r * dstride;
+            const uint64_t n_here = std::min(hi, (r + 1) * dstride) - o;
+            uint8_t* d = dst + (o - off);
             if (c < row_bytes) {
-                const uint64_t n = std::min(len, row_bytes - c);
-                memcpy(dst + off, src + r * src_stride + c, n);
-                if (len > n) memset(dst + off + n, 0, len - n);
+                const uint64_t n = std::min(n_here, row_bytes - c);
+                memcpy(d, src + r * src_stride + c, n);
+                if (n_here > n) memset(d + n, 0, n_here - n);
             } else {
-                memset(dst + off, 0, len);
+                memset(d, 0, n_here);
             }
-            off += len;
+            o += n_here;
         }
     };
     std::vector<std::thread> pool;
@@ -464,6 +464,11 @@ void pack_rows(uint8_t* dst, const uint8_t* src, uint32_t nr, uint64_t src_strid
     work(0);
     for (unsigned t : inline_parts) work(t);
     for (auto& th : pool) th.join();
+}
+
+void pack_rows(uint8_t* dst, const uint8_t* src, uint32_t nr, uint64_t src_stride, uint64_t row_bytes,
+               uint64_t dstride) {
+    pack_range(dst, src, src_stride, row_bytes, dstride, 0, (uint64_t)nr * dstride);
 }
 
 }  // namespace pir
@@ -734,17 +739,15 @@ static bool pinned_host(const void* p, size_t bytes) {
     return true;
 }
 
-// Rows per staging half for the pageable path (about 16 MiB, at least one).
-static uint32_t stage_rows(uint64_t dstride) {
-    const uint64_t r = (16ull << 20) / dstride;
-    return r < 1 ? 1u : (uint32_t)r;
-}
+// Bytes per staging half for the pageable path.
+constexpr uint64_t kStageChunk = 16ull << 20;
 
 // Synchronous path: upload, scan, download on a pooled stream.  Pinned
 // selection rows (and a pinned answer buffer) are copied straight to (from)
-// the device with a pitched copy; pageable rows are packed into two pinned
-// staging halves in turn, so that packing one chunk of rows overlaps the
-// upload of the previous one.
+// the device with a pitched copy; pageable rows are packed, in the device
+// layout, into two pinned staging halves of 16 MiB in turn (a chunk may end
+// inside a row), so that packing one chunk overlaps the upload of the one
+// before.
 int pir_dpxor_batch(pir_db* d, const uint8_t* sel_bits, uint64_t sel_stride, uint32_t q, uint8_t* out) {
     clear_error();
     Db* db = reinterpret_cast<Db*>(d);
@@ -784,19 +787,17 @@ int pir_dpxor_batch(pir_db* d, const uint8_t* sel_bits, uint64_t sel_stride, uin
                                   ex->stream)) != hipSuccess)
             return hip_fail(e, "selection upload");
     } else {
-        const uint32_t rows = std::min<uint32_t>(q, stage_rows(dstride));
-        if ((e = ex->h_sel.ensure((size_t)2 * rows * dstride)) != hipSuccess)
-            return hip_fail(e, "pinned selection staging");
-        for (uint32_t r0 = 0, c = 0; r0 < q; r0 += rows, ++c) {
-            const uint32_t nr = std::min<uint32_t>(rows, q - r0);
-            const int half = c & 1;
+        const uint64_t chunk = std::min<uint64_t>(sel_bytes, kStageChunk);
+        if ((e = ex->h_sel.ensure((size_t)(2 * chunk))) != hipSuccess) return hip_fail(e, "pinned selection staging");
+        for (uint64_t off = 0, c = 0; off < sel_bytes; off += chunk, ++c) {
+            const uint64_t len = std::min<uint64_t>(chunk, sel_bytes - off);
+            const int half = (int)(c & 1);
             // the upload that last used this half has finished
             if (c >= 2 && (e = hipEventSynchronize(ex->staged[half])) != hipSuccess)
                 return hip_fail(e, "selection staging");
-            uint8_t* hs = (uint8_t*)ex->h_sel.ptr + (size_t)half * rows * dstride;
-            pack_rows(hs, sel_bits + (size_t)r0 * sel_stride, nr, sel_stride, row_bytes, dstride);
-            if ((e = hipMemcpyAsync(ds + (size_t)r0 * dstride, hs, (size_t)nr * dstride, hipMemcpyHostToDevice,
-                                    ex->stream)) != hipSuccess)
+            uint8_t* hs = (uint8_t*)ex->h_sel.ptr + half * chunk;
+            pack_range(hs, sel_bits, sel_stride, row_bytes, dstride, off, len);
+            if ((e = hipMemcpyAsync(ds + off, hs, (size_t)len, hipMemcpyHostToDevice, ex->stream)) != hipSuccess)
                 return hip_fail(e, "selection upload");
             if ((e = hipEventRecord(ex->staged[half], ex->stream)) != hipSuccess)
                 return hip_fail(e, "selection staging");

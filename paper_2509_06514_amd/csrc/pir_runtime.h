@@ -31,10 +31,13 @@ struct DevBuf {
     hipError_t ensure(size_t want);
 };
 
-// Packs nr host rows (src, src_stride bytes apart, row_bytes each) into
-// dst at a pitch of dstride bytes, zero-filling each row's tail.  Copies of
-// 8 MiB or more are split over up to 8 host threads; a thread that cannot be
-// started leaves its share to the caller's thread.
+// Host rows (src, src_stride bytes apart, row_bytes each) laid out at a
+// pitch of dstride bytes, each row's tail zero: pack_range writes bytes
+// [off, off + len) of that layout to dst[0, len), pack_rows its first nr
+// rows.  Copies of 8 MiB or more are split over up to 8 host threads; a
+// thread that cannot be started leaves its share to the caller's thread.
+void pack_range(uint8_t* dst, const uint8_t* src, uint64_t src_stride, uint64_t row_bytes, uint64_t dstride,
+                uint64_t off, uint64_t len);
 void pack_rows(uint8_t* dst, const uint8_t* src, uint32_t nr, uint64_t src_stride, uint64_t row_bytes,
                uint64_t dstride);
 
