@@ -34,17 +34,51 @@ CONFIGS = {
     "n23r256q256": (1 << 23, 256, 256),
 }
 
-VARIANT_DTYPE = {1: "u32", 2: "int8", 3: "fp4"}
+# The arithmetic is exact GF(2) in every variant: bitwise XOR on 32-bit words,
+# or 0/1 operands on the matrix cores with exact integer counts (fp32 counts
+# stay below 2^24 per record group) whose parity is the answer bit.
+VARIANT_DTYPE = {1: "u32 (bitwise select-XOR, exact GF(2))",
+                 2: "gf2-exact (int8 0/1 operands, int32 counts)",
+                 3: "gf2-exact (fp4 0/1 operands, fp32 counts <= 2^24)"}
+
+
+def affinity_threads():
+    """Host threads this process may run on."""
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except (AttributeError, OSError):
+        return max(1, os.cpu_count() or 1)
+
+
+def host_info():
+    """The host the CPU baseline runs on: logical CPUs, this process's share, model name."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity_threads": affinity_threads(), "cpu_model": model}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash(src="pir_kernels.hip"):
+SCAN_SOURCES = ("pir_kernels.hip", "pir_scan_common.h")
+
+
+def kernel_source_hash(srcs=SCAN_SOURCES):
+    """First 16 hex digits of the SHA-256 of the named kernel sources, concatenated."""
+    if isinstance(srcs, str):
+        srcs = (srcs,)
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2509_06514_amd", "csrc", src), "rb") as f:
-        h.update(f.read())
+    for src in srcs:
+        with open(os.path.join(ROOT, "paper_2509_06514_amd", "csrc", src), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -103,8 +137,9 @@ def time_steps(fn, steps, torch):
     return wall, per
 
 
-def roofline_for(variant, n, r, q, stage1_ms_avg, traffic):
-    """Roofline record for the stage-1 kernel of one launch."""
+def roofline_for(variant, n, r, q, stage1_ms_avg, traffic, roof=None):
+    """Roofline record for the stage-1 kernel of one launch (roof: the measured
+    streaming-read roof, reported beside the fraction of the 8 TB/s spec)."""
     alg_bytes = n * r + q * ((n + 7) // 8) + q * r
     t_s = stage1_ms_avg / 1e3
     hbm_time = alg_bytes / (HBM_PEAK_GBS * 1e9)
@@ -126,36 +161,124 @@ def roofline_for(variant, n, r, q, stage1_ms_avg, traffic):
                     "frac": ach / MFMA_PEAK_TFLOPS[dt], "traffic": traffic,
                     "algorithmic_flops_per_launch": flops, "avg_launch_ms": stage1_ms_avg}
     ach = alg_bytes / t_s / 1e9
-    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
-            "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": stage1_ms_avg}
+    rec = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
+           "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": stage1_ms_avg}
+    if roof:
+        rec["read_roof_gbs"] = roof
+        rec["frac_of_read_roof"] = ach / roof
+    return rec
 
 
 def cpu_baseline(db_host, sel_rows, n, r, sample_queries, threads):
     """The oracle on the host: `sample_queries` full queries on one thread, then one
     query per thread on `threads` threads at once (the CPU-PIR arrangement of one
-    query per core).  The C oracle releases the interpreter lock while it runs."""
+    query per core).  The C oracle releases the interpreter lock while it runs.
+    Returns the record and the oracle's answers to rows 0 .. threads-1 (row i mod Q)."""
     import threading
+
+    import numpy as np
 
     import oracle
 
     t0 = time.perf_counter()
     for i in range(sample_queries):
-        oracle.dpxor(db_host, sel_rows[i])
+        oracle.dpxor(db_host, sel_rows[i % len(sel_rows)])
     dt1 = time.perf_counter() - t0
-    ths = [threading.Thread(target=oracle.dpxor, args=(db_host, sel_rows[i % len(sel_rows)]))
-           for i in range(threads)]
+    answers = np.empty((threads, r), np.uint8)
+
+    def one(i):
+        answers[i] = oracle.dpxor(db_host, sel_rows[i % len(sel_rows)])
+
+    ths = [threading.Thread(target=one, args=(i,)) for i in range(threads)]
     t0 = time.perf_counter()
     for th in ths:
         th.start()
     for th in ths:
         th.join()
     dtn = time.perf_counter() - t0
-    return {"value": threads / dtn, "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": f"{threads} full queries (N={n}, R={r}), one per host thread, {dtn:.1f} s; "
-                      f"single thread: {sample_queries} queries in {dt1:.1f} s",
-            "single_thread": {"value": sample_queries / dt1, "unit": "queries/s", "cores": 1,
-                              "db_gbs_scanned": sample_queries * n * r / dt1 / 1e9}}
+    rec = {"value": threads / dtn, "unit": "queries/s", "cores": threads, "kind": "oracle",
+           "host": host_info(),
+           "build": "gcc -O2 -std=c11 (plain loops, no intrinsics)",
+           "sample": f"{threads} full queries (N={n}, R={r}), one per host thread at once, {dtn:.1f} s; "
+                     f"single thread: {sample_queries} queries in {dt1:.1f} s",
+           "single_thread": {"value": sample_queries / dt1, "unit": "queries/s", "cores": 1,
+                             "db_gbs_scanned": sample_queries * n * r / dt1 / 1e9}}
+    return rec, answers
+
+
+def read_roof(ctx, nbytes, torch, reps=5):
+    """Practical HBM read roof: the library's streaming-read probe over a fresh
+    device buffer of `nbytes`, best mean over unroll x workgroup counts."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0").fill_(0x5A)
+    sink = torch.empty((1 << 16, 4), dtype=torch.int32, device="cuda:0")
+    best = None
+    for unroll in (4, 8, 16):
+        for wgs in (1024, 2048, 4096, 8192, 16384, 32768):
+            ctx.read_probe_async(src, sink, unroll=unroll, workgroups=wgs)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                ctx.read_probe_async(src, sink, unroll=unroll, workgroups=wgs)
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            gbs = nbytes / (ms / 1e3) / 1e9
+            if best is None or gbs > best["achieved_gbs"]:
+                best = {"achieved_gbs": gbs, "ms": ms, "unroll": unroll, "workgroups": wgs}
+    del src, sink
+    best.update({"bytes": nbytes, "frac_of_spec": best["achieved_gbs"] / HBM_PEAK_GBS,
+                 "kernel": "k_read_probe (pir_read_probe_async): 16-byte non-temporal loads, "
+                           "contiguous range per workgroup"})
+    log(f"read roof: {best['achieved_gbs']:.0f} GB/s (unroll {best['unroll']}, {best['workgroups']} workgroups)")
+    return best
+
+
+def phase_breakdown(ctx, db, sel_host, stride, r, qs, steps, torch):
+    """Table 1's phases on the device stream for each Q: selection upload from
+    pinned host memory, stage 1, stage 2, answer download to pinned host memory
+    (HIP events around each phase, means over `steps` rounds)."""
+    dev = torch.device("cuda:0")
+    out = {}
+    for qq in qs:
+        h_sel = torch.from_numpy(sel_host[:qq]).pin_memory()
+        h_out = torch.empty((qq, r), dtype=torch.uint8).pin_memory()
+        d_sel = torch.empty((qq, stride), dtype=torch.uint8, device=dev)
+        d_out = torch.empty((qq, r), dtype=torch.uint8, device=dev)
+        d_sel.copy_(h_sel)
+        db.dpxor_batch_async(d_sel, qq, d_out, sel_stride=stride)
+        torch.cuda.synchronize()
+        ctx.timing(True)
+        ctx.timing_read(reset=True)
+        evs = []
+        for _ in range(steps):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            e[0].record()
+            d_sel.copy_(h_sel, non_blocking=True)
+            e[1].record()
+            db.dpxor_batch_async(d_sel, qq, d_out, sel_stride=stride)
+            e[2].record()
+            h_out.copy_(d_out, non_blocking=True)
+            e[3].record()
+            evs.append(e)
+        torch.cuda.synchronize()
+        t = ctx.timing_read(reset=True)
+        ctx.timing(False)
+        h2d = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
+        scan = sum(e[1].elapsed_time(e[2]) for e in evs) / steps
+        d2h = sum(e[2].elapsed_time(e[3]) for e in evs) / steps
+        s1 = t["stage1_ms"] / max(1, t["stage1_launches"])
+        s2 = t["stage2_ms"] / max(1, t["stage2_launches"])
+        total = h2d + scan + d2h
+        rec = {"sel_h2d_ms": h2d, "stage1_ms": s1, "stage2_ms": s2, "answer_d2h_ms": d2h,
+               "scan_enqueue_to_done_ms": scan, "total_ms": total,
+               "share_pct": {"sel_h2d": 100 * h2d / total, "stage1": 100 * s1 / total,
+                             "stage2": 100 * s2 / total, "answer_d2h": 100 * d2h / total},
+               "sel_h2d_gbs": qq * stride / (h2d / 1e3) / 1e9}
+        out[f"q{qq}"] = rec
+        log(f"phases Q={qq}: H2D {h2d:.3f} ms, stage1 {s1:.3f} ms, stage2 {s2:.4f} ms, D2H {d2h:.4f} ms")
+        del h_sel, h_out, d_sel, d_out
+    return out
 
 
 # VALU operations per tree-node expansion of the DPF evaluation (AES-128 with
@@ -447,10 +570,12 @@ def serve_bench(args):
     """Open-loop Poisson arrivals over three resident databases (continuous batching).
 
     Each rate runs for at least 10 s or 20k requests (and at least
-    args.serve_seconds); each request goes to a database
-    drawn uniformly; selections come from a pre-generated pool per database
-    (contents do not change the scan's cost).  Latency is submit -> answer in
-    host memory, measured by the server.
+    args.serve_seconds); each request goes to a database drawn uniformly;
+    selections come from a pool of 16 per database (contents do not change the
+    scan's cost).  Latency is submit -> answer in host memory, measured by the
+    server.  After each rate, the last answer written to every output slot is
+    compared with the same selection answered alone by the library's
+    synchronous call ("alone vs in the mix").
     """
     import threading
 
@@ -459,6 +584,9 @@ def serve_bench(args):
     import synth
     import paper_2509_06514_amd as pir
 
+    # submitters sleep until their next arrival (no spinning) and hand the
+    # interpreter lock on quickly, so arrivals are not bunched by the lock
+    sys.setswitchinterval(100e-6)
     ctx = pir.Context(0)
     hosts, dbs = [], []
     for k, (n, r) in enumerate(SERVE_DBS):
@@ -476,6 +604,7 @@ def serve_bench(args):
             qq *= 2
         log(f"serve: tuned DB{k} for batches of 1 .. {args.serve_qmax}")
     pool = [synth.selections(n, 16, seed=synth.S_SEL + 50 + k) for k, (n, r) in enumerate(SERVE_DBS)]
+    alone = [d.dpxor_batch(p) for d, p in zip(dbs, pool)]  # each pool row answered on its own call
     if args.serve_keys:
         # requests are DPF keys: a pool per database (the server's cost does not
         # depend on alpha), plus one key pair per database checked afterwards
@@ -492,11 +621,13 @@ def serve_bench(args):
     results = []
     rates = [int(x) for x in (args.serve_key_rates if args.serve_keys else args.serve_rates).split(",")]
     threads_n = args.serve_threads
+    slots_per_thread = 512
     for rate in rates:
         srv = pir.Server(ctx, q_max=args.serve_qmax, max_wait_us=args.serve_wait_us, n_slots=args.serve_slots,
                          queue_cap=1 << 20)
         ids = [srv.add_db(d) for d in dbs]
-        outs = [np.zeros((4096, r), np.uint8) for (n, r) in SERVE_DBS]
+        outs = [np.zeros((threads_n * slots_per_thread, r), np.uint8) for (n, r) in SERVE_DBS]
+        last = [np.full(threads_n * slots_per_thread, -1, np.int64) for _ in SERVE_DBS]  # pool row last written
         # at least 10 s or 20k requests per rate (whichever comes first), at least serve_seconds
         dur = min(10.0, max(args.serve_seconds, 20000.0 / rate))
         stop_at = time.perf_counter() + dur
@@ -510,19 +641,19 @@ def serve_bench(args):
             lib_submit = srv.submit_key_raw if args.serve_keys else srv.submit_raw
             while True:
                 t += rng.exponential(threads_n / rate)
-                now = time.perf_counter()
                 if t > stop_at:
                     break
-                if t > now:
-                    time.sleep(max(0.0, t - now - 50e-6))
-                    while time.perf_counter() < t:
-                        pass
+                dt = t - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
                 w = int(rng.integers(0, 3))
                 src = kpool[w][k % 16] if args.serve_keys else pool[w][k % 16]
-                out = outs[w][(tid * 512 + k) % 4096]
+                slot = tid * slots_per_thread + k % slots_per_thread
+                out = outs[w][slot]
                 rc, tk = lib_submit(ids[w], src.ctypes.data, out.ctypes.data)
                 if rc == 0:
                     pending[tid].append(tk)
+                    last[w][slot] = k % 16
                 else:
                     rejected[tid] += 1
                 k += 1
@@ -550,11 +681,21 @@ def serve_bench(args):
         hist = {f"{1 << i}-{(2 << i) - 1}": c for i, c in enumerate(st["batch_hist"]) if c}
         rec = {"offered_qps": rate, "seconds": dur, "achieved_qps": st["completed"] / dur,
                "completed": st["completed"], "rejected": st["rejected"] + sum(rejected),
+               "blocked_submits": st["blocked_submits"],
                "p50_ms": st["p50_us"] / 1e3, "p99_ms": st["p99_us"] / 1e3, "mean_ms": st["mean_us"] / 1e3,
+               "max_ms": st["max_us"] / 1e3,
                "batches": st["batches"], "batch_hist": hist, "max_inflight": st["max_inflight"],
                "h2d_GBps": st["h2d_bytes"] / dur / 1e9}
         if check is not None:
             rec["two_server_check"] = bool(check)
+        else:
+            checked = same = 0
+            for w in range(3):
+                for slot in np.nonzero(last[w] >= 0)[0]:
+                    checked += 1
+                    same += bool(np.array_equal(outs[w][slot], alone[w][last[w][slot]]))
+            rec["answers_checked_vs_alone"] = checked
+            rec["answers_same_as_alone"] = same == checked
         log(f"serve rate {rate}: {json.dumps(rec)}")
         results.append(rec)
     for d in dbs:
@@ -573,8 +714,9 @@ def main():
     ap.add_argument("--variants", action="store_true",
                     help="also time the best plan of each kernel family (VALU, int8 MFMA, fp4 MFMA) for Q")
     ap.add_argument("--cpu-sample", type=int, default=2, help="oracle queries for cpu_baseline (0 = skip)")
-    ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1),
-                    help="host threads for the all-core oracle baseline (one query each)")
+    ap.add_argument("--cpu-threads", type=int, default=affinity_threads(),
+                    help="host threads for the all-core oracle baseline (one query each; default: every "
+                         "thread this process may run on)")
     ap.add_argument("--sel-fill", default="random", choices=["random", "zeros", "ones"],
                     help="selection contents (zeros/ones: the scan must read the same bytes)")
     ap.add_argument("--serve-keys", action="store_true", help="serving sweep with DPF keys as requests")
@@ -595,6 +737,9 @@ def main():
     ap.add_argument("--serve-qmax", type=int, default=64)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-wait-us", type=int, default=200)
+    ap.add_argument("--no-read-roof", action="store_true", help="skip the streaming-read roof probe")
+    ap.add_argument("--phase-steps", type=int, default=10,
+                    help="rounds of the per-phase breakdown (selection upload, stages, answer download; 0 = skip)")
     ap.add_argument("--calib-copy-gib", type=int, default=0,
                     help="first run a plain device copy of this many GiB, 3 times (counter calibration)")
     args = ap.parse_args()
@@ -645,6 +790,7 @@ def main():
         sel_host[:] = 0 if args.sel_fill == "zeros" else 0xFF
 
     ctx = pir.Context(0)
+    roof = None if args.no_read_roof else read_roof(ctx, n * r, torch)
     t = time.perf_counter()
     db = ctx.load_db(db_host)
     log(f"loaded into HBM in {time.perf_counter() - t:.1f}s")
@@ -701,7 +847,8 @@ def main():
             "db_gbs_scanned": n * r / (ms1 / 1e3) / 1e9,
             "latency_ms": {"p50": percentile(per_1, 0.5), "p99": percentile(per_1, 0.99)},
             "cfg": cfg_1.as_dict(),
-            "roofline": roofline_for(cfg_1.variant, n, r, 1, s1_avg, load_traffic(n, r, 1, cfg_1)),
+            "roofline": roofline_for(cfg_1.variant, n, r, 1, s1_avg, load_traffic(n, r, 1, cfg_1),
+                                     roof["achieved_gbs"] if roof else None),
         }
         log(f"Q=1: {ms1:.3f} ms/query, {single['db_gbs_scanned']:.0f} GB/s scanned, stage1 avg {s1_avg:.3f} ms")
 
@@ -729,16 +876,22 @@ def main():
         "db_gbs_scanned": n * r / (ms_step / 1e3) / 1e9,
         "latency_ms": {"p50": percentile(per_q, 0.5), "p99": percentile(per_q, 0.99)},
         "stage_ms": {"stage1_avg": s1q, "stage2_avg": tq["stage2_ms"] / max(1, tq["stage2_launches"])},
-        "roofline": roofline_for(cfg_q.variant, n, r, q, s1q, load_traffic(n, r, q, cfg_q)),
+        "roofline": roofline_for(cfg_q.variant, n, r, q, s1q, load_traffic(n, r, q, cfg_q),
+                                 roof["achieved_gbs"] if roof else None),
     }
+    if roof:
+        result["read_roof"] = roof
     if single is not None:
         result["single_query"] = single
         result["batched_vs_single_qps"] = qps / single["queries_per_s"]
 
-    # correctness spot check of this run's answers: the two-server identity on row 0
-    # is covered by the tests; here only that the answers are not all zero
+    # this run's answers, compared with the oracle's rows when cpu_baseline runs
     ans = d_out.cpu().numpy()
     result["answers_nonzero"] = bool(ans.any())
+
+    if args.phase_steps > 0:
+        result["phases"] = phase_breakdown(ctx, db, sel_host, stride, r, [1, q] if q > 1 else [1],
+                                           args.phase_steps, torch)
 
     if args.host_steps > 0:
         result["host_path"] = host_path_bench(db, sel_host, n, r, q, args.host_steps, pir)
@@ -754,7 +907,12 @@ def main():
 
     if args.cpu_sample > 0:
         log(f"cpu_baseline: oracle on {args.cpu_sample} queries ...")
-        result["cpu_baseline"] = cpu_baseline(db_host, sel_host, n, r, args.cpu_sample, args.cpu_threads)
+        rec, want = cpu_baseline(db_host, sel_host, n, r, args.cpu_sample, args.cpu_threads)
+        result["cpu_baseline"] = rec
+        k = min(q, want.shape[0])
+        bad = [i for i in range(k) if not np.array_equal(ans[i], want[i])]
+        result["oracle_rows_match"] = {"rows_checked": k, "match": not bad, "mismatched_rows": bad[:16]}
+        log(f"oracle rows 0..{k - 1}: {'all match' if not bad else f'{len(bad)} differ'}")
     else:
         result["cpu_baseline"] = None
 

@@ -230,7 +230,12 @@ typedef struct pir_serve_config {
     uint32_t q_max;            /* largest batch per launch (<= PIR_MAX_BATCH; 0 = 64) */
     uint32_t max_wait_us;      /* a partial batch waits at most this long for company (0 = dispatch at once) */
     uint32_t n_slots;          /* concurrent in-flight batches (0 = 4) */
-    uint32_t queue_cap;        /* pending requests per database before PIR_E_BUSY (0 = 65536) */
+    uint32_t queue_cap;        /* queued (not yet dispatched) requests per database and kind before
+                                  PIR_E_BUSY (0 = 65536) */
+    uint32_t submit_wait_ms;   /* longest a submit waits for a free row of the pinned request ring
+                                  before PIR_E_BUSY (0 = 1000) */
+    uint64_t ring_bytes;       /* pinned selection ring per database (0 = 256 MiB); it holds at least
+                                  (n_slots + 1) * q_max rows and at most queue_cap + n_slots * q_max */
 } pir_serve_config;
 
 typedef struct pir_serve_stats {
@@ -250,6 +255,7 @@ typedef struct pir_serve_stats {
     uint32_t n_slots;
     uint64_t key_requests;    /* requests submitted as DPF keys */
     uint64_t updates_applied; /* record updates applied */
+    uint64_t blocked_submits; /* submits that waited for a free ring row */
 } pir_serve_stats;
 
 int pir_serve_create(pir_ctx* ctx, const pir_serve_config* cfg, pir_server** out);
@@ -259,10 +265,13 @@ int pir_serve_create(pir_ctx* ctx, const pir_serve_config* cfg, pir_server** out
 int pir_serve_add_db(pir_server* srv, pir_db* db, uint32_t* db_id);
 
 /*
- * Queue one query.  sel_bits (ceil(N/8) bytes) is copied before the call
- * returns; out (R bytes) must stay valid until pir_serve_wait or
- * pir_serve_poll reports completion.  Errors: PIR_E_NOTFOUND (db_id),
- * PIR_E_BUSY (queue full), PIR_E_SHUTDOWN.
+ * Queue one query.  sel_bits (ceil(N/8) bytes) is copied into the
+ * database's pinned request ring before the call returns; out (R bytes) must
+ * stay valid until pir_serve_wait or pir_serve_poll reports completion.
+ * Backpressure: when every ring row belongs to a queued or in-flight request
+ * the call blocks until a batch retires (at most submit_wait_ms).  Errors:
+ * PIR_E_NOTFOUND (db_id), PIR_E_BUSY (queue_cap requests already queued, or
+ * no ring row freed within submit_wait_ms), PIR_E_SHUTDOWN.
  */
 int pir_serve_submit(pir_server* srv, uint32_t db_id, const uint8_t* sel_bits, uint8_t* out,
                      uint64_t* ticket);
@@ -439,6 +448,24 @@ int pir_fp_inner_async(pir_fpdb* db, const void* d_v, uint64_t v_stride, uint32_
 /* Q queries, host in and out, synchronous: v holds q rows v_stride >= N
  * bytes apart, out receives q rows of L bytes. */
 int pir_fp_inner(pir_fpdb* db, const uint8_t* v, uint64_t v_stride, uint32_t q, uint8_t* out);
+
+/* ---------------------------------------------------------------- measurement */
+
+/*
+ * Streaming-read probe: the practical HBM read roof that the scans are
+ * measured against.  Reads every 16-byte chunk of d_src[0, bytes) once with
+ * non-temporal loads, `workgroups` workgroups each taking a contiguous range
+ * (unroll = 4, 8 or 16 loads in flight per lane), and writes the XOR of each
+ * workgroup's chunks to d_sink, one 16-byte word per workgroup launched.
+ * With C = bytes / 16 chunks, a workgroup takes P = ceil(C / workgroups)
+ * chunks and ceil(C / P) <= workgroups workgroups run; d_sink holds at least
+ * 16 * workgroups bytes and words past the launched ones are not written.
+ * The XOR of the written words is the XOR of all chunks.  Asynchronous on hip_stream; device buffers, 16-byte aligned; bytes
+ * a positive multiple of 16; 1 <= workgroups <= 2^20.  Errors: PIR_E_INVAL,
+ * PIR_E_DEVICE.
+ */
+int pir_read_probe_async(pir_ctx* ctx, const void* d_src, uint64_t bytes, uint32_t unroll, uint32_t workgroups,
+                         void* d_sink, void* hip_stream);
 
 /* ---------------------------------------------------------------- memory */
 

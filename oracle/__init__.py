@@ -114,6 +114,46 @@ def dpxor_batch(db, sel_rows):
     return out
 
 
+def host_threads():
+    """Host threads this process may run on (its CPU affinity set)."""
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except (AttributeError, OSError):
+        return max(1, os.cpu_count() or 1)
+
+
+def dpxor_rows(db, sel_rows, rows=None, threads=None):
+    """Answers of the selection rows `rows` (default: all) of a (Q, stride) array,
+    each computed by the single-threaded oracle; rows run on up to `threads` host
+    threads at once (the C oracle releases the interpreter lock).  Returns a
+    (len(rows), R) array in the order of `rows`."""
+    import threading
+
+    db = _u8(db)
+    sel_rows = _u8(sel_rows)
+    rows = list(range(sel_rows.shape[0])) if rows is None else list(rows)
+    out = np.empty((len(rows), db.shape[1]), dtype=np.uint8)
+    nxt = [0]
+    lock = threading.Lock()
+
+    def work():
+        while True:
+            with lock:
+                k = nxt[0]
+                nxt[0] += 1
+            if k >= len(rows):
+                return
+            out[k] = dpxor(db, sel_rows[rows[k]])
+
+    t = min(len(rows), threads or host_threads())
+    ths = [threading.Thread(target=work) for _ in range(t)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    return out
+
+
 def reconstruct(r1, r2):
     """Client step of the two-server scheme: D[i] = r1 XOR r2."""
     r1, r2 = _u8(r1), _u8(r2)

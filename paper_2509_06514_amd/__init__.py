@@ -188,6 +188,18 @@ class Context:
                                        ctypes.c_void_p(d_sel.data_ptr()), sel_stride, _stream_handle(stream)),
               "pir_dpf_eval_async")
 
+    def read_probe_async(self, d_src, d_sink, unroll=8, workgroups=4096, stream=None):
+        """Streaming-read probe over a device tensor (every 16-byte chunk read once);
+        d_sink receives one 16-byte XOR word per workgroup."""
+        nbytes = d_src.numel() * d_src.element_size()
+        if d_src.device.type != "cuda" or d_sink.device.type != "cuda":
+            raise ValueError("device tensors required")
+        if d_sink.numel() * d_sink.element_size() < 16 * workgroups:
+            raise ValueError("d_sink too small")
+        check(lib().pir_read_probe_async(self._h, ctypes.c_void_p(d_src.data_ptr()), nbytes, unroll, workgroups,
+                                         ctypes.c_void_p(d_sink.data_ptr()), _stream_handle(stream)),
+              "pir_read_probe_async")
+
     def close(self):
         if self._h:
             check(lib().pir_ctx_destroy(self._h), "pir_ctx_destroy")
@@ -370,8 +382,10 @@ class FpDatabase:
 class Server:
     """Continuous-batching server (pir_server)."""
 
-    def __init__(self, ctx, hbm_budget_bytes=0, q_max=64, max_wait_us=0, n_slots=4, queue_cap=0):
-        cfg = _native.pir_serve_config(hbm_budget_bytes, q_max, max_wait_us, n_slots, queue_cap)
+    def __init__(self, ctx, hbm_budget_bytes=0, q_max=64, max_wait_us=0, n_slots=4, queue_cap=0,
+                 submit_wait_ms=0, ring_bytes=0):
+        cfg = _native.pir_serve_config(hbm_budget_bytes, q_max, max_wait_us, n_slots, queue_cap, submit_wait_ms,
+                                       ring_bytes)
         h = ctypes.c_void_p()
         check(lib().pir_serve_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)), "pir_serve_create")
         self._h = h

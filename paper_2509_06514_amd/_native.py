@@ -52,7 +52,8 @@ class pir_timing(ctypes.Structure):
 class pir_serve_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("q_max", ctypes.c_uint32),
                 ("max_wait_us", ctypes.c_uint32), ("n_slots", ctypes.c_uint32),
-                ("queue_cap", ctypes.c_uint32)]
+                ("queue_cap", ctypes.c_uint32), ("submit_wait_ms", ctypes.c_uint32),
+                ("ring_bytes", ctypes.c_uint64)]
 
 
 class pir_serve_stats(ctypes.Structure):
@@ -63,7 +64,8 @@ class pir_serve_stats(ctypes.Structure):
                 ("elapsed_s", ctypes.c_double), ("qps", ctypes.c_double),
                 ("batch_hist", ctypes.c_uint64 * 13), ("h2d_bytes", ctypes.c_uint64),
                 ("max_inflight", ctypes.c_uint32), ("n_slots", ctypes.c_uint32),
-                ("key_requests", ctypes.c_uint64), ("updates_applied", ctypes.c_uint64)]
+                ("key_requests", ctypes.c_uint64), ("updates_applied", ctypes.c_uint64),
+                ("blocked_submits", ctypes.c_uint64)]
 
 
 _P = ctypes.c_void_p
@@ -116,6 +118,7 @@ SIGNATURES = {
     "pir_fp_v_stride": (_U64, [_P]),
     "pir_fp_inner_async": (_I, [_P, _P, _U64, _U32, _P, _P]),
     "pir_fp_inner": (_I, [_P, _P, _U64, _U32, _P]),
+    "pir_read_probe_async": (_I, [_P, _P, _U64, _U32, _U32, _P, _P]),
     "pir_host_alloc": (_P, [ctypes.c_size_t]),
     "pir_host_free": (None, [_P]),
 }

@@ -14,8 +14,14 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpir.so")
 ARCH = "gfx950"
 
-SOURCES = ["pir_kernels.hip", "pir_dpf.hip", "pir_fp.hip", "pir_runtime.cpp", "pir_dpf_api.cpp",
-           "pir_fp_api.cpp", "pir_serve.cpp"]
+SOURCES = ["pir_kernels.hip", "pir_dpf.hip", "pir_fp.hip", "pir_probe.hip",
+           "pir_runtime.cpp", "pir_dpf_api.cpp", "pir_fp_api.cpp", "pir_serve.cpp"]
+
+# Sources whose matrix-core accumulators may live in the accumulation
+# registers (AGPRs); everywhere else they live in ordinary VGPRs (no AGPR
+# copies per step).
+AGPR_SOURCES = set()
+VGPR_FORM = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}",
@@ -26,8 +32,6 @@ HIPCC_FLAGS = [
     "-Wno-unused-result",
     # packed fp32 VALU forms are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # matrix-core accumulators live in ordinary VGPRs (no AGPR copies per step)
-    "-mllvm", "-amdgpu-mfma-vgpr-form",
     f"-I{INCLUDE}",
     f"-I{CSRC}",
 ]
@@ -50,7 +54,8 @@ def build(verbose=False):
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(objdir, src + ".o")
-        cmd = [hipcc, *HIPCC_FLAGS, "-c", path, "-o", obj]
+        flags = HIPCC_FLAGS if src in AGPR_SOURCES else HIPCC_FLAGS + VGPR_FORM
+        cmd = [hipcc, *flags, "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

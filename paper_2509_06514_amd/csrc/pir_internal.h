@@ -78,6 +78,9 @@ hipError_t launch_stage1_valu(const Geometry& g, const Plan& p, const void* db, 
 bool mfma_supported(uint32_t variant, const Geometry& g, uint32_t qt, uint32_t unroll);
 hipError_t launch_stage1_mfma(const Geometry& g, const Plan& p, const void* db, const uint32_t* sel,
                               uint64_t stride_words, uint32_t q, uint8_t* partials, hipStream_t s);
+// Raise the dynamic-LDS limit of every stage-1 ring kernel on the current
+// device (done when a context is created, so that no scan call needs to)
+hipError_t prepare_scan_kernels();
 hipError_t launch_stage2(const Geometry& g, uint32_t groups, uint32_t q, const uint8_t* partials,
                          uint8_t* out, hipStream_t s);
 // natural row-major records [rec0, rec0 + nrec) -> bit-sliced blocks starting at rec0 / 32

@@ -14,15 +14,14 @@
 #include <hip/hip_runtime.h>
 
 #include "pir_internal.h"
+#include "pir_scan_common.h"
 
 namespace pir {
 
 namespace {
 
-constexpr int kThreads = 256;  // 4 waves of 64
-constexpr int kWaves = kThreads / 64;
+using namespace scan;
 
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // One 16-byte chunk per lane (global_load_dwordx4); NT marks it streaming.
 template <bool NT>
@@ -31,22 +30,6 @@ __device__ __forceinline__ u32x4 load16(const u32x4* p) {
     return *p;
 }
 
-struct Stage1Params {
-    uint64_t n_units;
-    uint64_t units_per_group;
-    uint64_t stride_words;  // selection row pitch in 32-bit words
-    uint64_t nb;            // blocks holding records (selection words per row)
-    uint32_t q_total;
-    uint32_t groups;
-    uint32_t n_ct;
-    uint32_t n_qt;
-    uint32_t cpb;         // chunks per block
-    uint32_t bpw;         // blocks per unit
-    uint32_t lpb;         // lanes per block
-    uint32_t tile_bytes;  // record bytes per column tile
-    uint32_t R;
-    uint32_t rpad;
-};
 
 __device__ __forceinline__ uint32_t parity4(const u32x4& a) {
     return (__builtin_popcount(a.x) & 1u) | ((__builtin_popcount(a.y) & 1u) << 1) |
@@ -65,23 +48,6 @@ __device__ __forceinline__ void sel_xor(u32x4& acc, const u32x4& d, uint32_t s) 
     acc.w = xor_and(acc.w, d.w, s);
 }
 
-// Workgroup -> (record group, column tile, query tile).  Workgroups are
-// dispatched round-robin over the 8 XCDs; consecutive workgroups on one XCD
-// get the column/query tiles of the same record group, so the selection
-// words and database chunks they share meet in that XCD's L2.
-__device__ __forceinline__ bool decode_block(uint32_t groups, uint32_t n_ct, uint32_t n_qt,
-                                             uint32_t& group, uint32_t& ct, uint32_t& qt) {
-    const uint32_t total = groups * n_ct * n_qt;
-    const uint32_t per_xcd = (total + 7) / 8;
-    const uint32_t v = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    if (v >= total) return false;
-    const uint32_t co = n_ct * n_qt;
-    group = v / co;
-    const uint32_t rem = v - group * co;
-    ct = rem / n_qt;
-    qt = rem - ct * n_qt;
-    return true;
-}
 
 // Stage 1, vector-ALU variant.  QT queries per workgroup, U units per wave
 // iteration (U independent 16-byte loads in flight per lane).
@@ -203,60 +169,7 @@ k_stage1_valu(const u32x4* __restrict__ db, const uint32_t* __restrict__ sel,
 // sub-step s.  Column tile t of lane j is bit column 64w + 4j + t, so a lane
 // reads its 4 columns with one 16-byte load.
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
-typedef int32_t i32x8 __attribute__((ext_vector_type(8)));
 
-constexpr uint32_t kMfmaBlocksPerStep = 16;
-
-// s_waitcnt with vmcnt <= N and no wait on the other counters (gfx9
-// encoding: vmcnt[3:0] bits 3:0, vmcnt[5:4] bits 15:14, expcnt 6:4,
-// lgkmcnt 11:8).
-template <int N>
-__device__ __forceinline__ void wait_vmcnt() {
-    static_assert(N >= 0 && N < 64, "vmcnt range");
-    __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
-}
-
-// Workgroup barrier without the memory fences of __syncthreads (which would
-// wait for every load in flight); the clobber keeps LDS accesses on their
-// side of it.
-__device__ __forceinline__ void wg_barrier() { asm volatile("s_barrier" ::: "memory"); }
-
-// 32 records of one word -> 32 E2M1 values, element (dword t, nibble n) =
-// record 4n + t.  The selection side (A, record order) and the database side
-// (B, stored order) use reciprocal values so that every product of two set
-// bits is exactly 1.0:
-//   t:    0     1     2     3
-//   A:   0.5   1.0   2.0   2.0     (E2M1 0b0001, 0b0010, 0b0100, 0b0100)
-//   B:   2.0   1.0   0.5   0.5
-// Each record is taken where it already sits in its nibble when that position
-// carries the wanted value (a mask only); nibble bit 3 would be the sign, so
-// record 4n+3 is shifted down on both sides.
-__device__ __forceinline__ i32x8 spread_fp4_a(uint32_t w) {  // w in record order
-    i32x8 r;
-    r[0] = (int32_t)(w & 0x11111111u);          // record 4n   at bit 0: 0.5
-    r[1] = (int32_t)(w & 0x22222222u);          // record 4n+1 at bit 1: 1.0
-    r[2] = (int32_t)(w & 0x44444444u);          // record 4n+2 at bit 2: 2.0
-    r[3] = (int32_t)((w >> 1) & 0x44444444u);   // record 4n+3 to bit 2: 2.0
-    r[4] = 0;
-    r[5] = 0;
-    r[6] = 0;
-    r[7] = 0;
-    return r;
-}
-__device__ __forceinline__ i32x8 spread_fp4_b(uint32_t w) {  // w in stored order
-    i32x8 r;
-    r[0] = (int32_t)(w & 0x44444444u);          // record 4n   stored at bit 2: 2.0
-    r[1] = (int32_t)(w & 0x22222222u);          // record 4n+1 at bit 1: 1.0
-    r[2] = (int32_t)(w & 0x11111111u);          // record 4n+2 stored at bit 0: 0.5
-    r[3] = (int32_t)((w >> 3) & 0x11111111u);   // record 4n+3 to bit 0: 0.5
-    r[4] = 0;
-    r[5] = 0;
-    r[6] = 0;
-    r[7] = 0;
-    return r;
-}
 
 // 32 records -> 32 int8 0/1 values in two 16-element halves: dword t, byte
 // m holds record 8m + t (half 0: t = 0..3, half 1: t = 4..7).  Record
@@ -542,7 +455,6 @@ __device__ __forceinline__ void lds_read_16(uint32_t r, u32x4 (&v)[16]) {
 // (vmcnt) and a barrier makes every wave's part visible; the same barrier
 // tells the wave that refills a stage that everyone has read it.  Stage
 // operands are read by lds_read_step, whose own lgkmcnt wait completes them.
-constexpr uint32_t kStageDbBytes = 16 * 256 * 4;
 
 template <int MT>
 __host__ __device__ constexpr uint32_t ring_bytes(int stages) {
@@ -759,19 +671,7 @@ k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
         }
 }
 
-typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
-// A wave-uniform pointer re-read through v_readfirstlane.  The loads below
-// add a 32-bit lane offset to it; without this the compiler folds base and
-// offset into one 64-bit pointer per lane and load, kept in vector registers
-// and advanced with vector adds every step (12 of them per step instead of
-// the 8 that forming each address from the scalar base takes).
-__device__ __forceinline__ const uint8_t* uniform_ptr(const uint8_t* p) {
-    const uint64_t v = reinterpret_cast<uint64_t>(p);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return reinterpret_cast<const uint8_t*>(((uint64_t)hi << 32) | lo);
-}
 
 // Operand reads of one K-step for the split-K kernel: two sub-steps of two
 // database chunks (columns +0 and +64 words) at `b` and `b` + 1 KiB, and the
@@ -1420,7 +1320,11 @@ static hipError_t launch_ks(dim3 grid, hipStream_t s, const uint32_t* db, const 
 
 static hipError_t launch_ksw(dim3 grid, hipStream_t s, const uint32_t* db, const uint32_t* sel, uint8_t* partials,
                              const Stage1Params& p) {
-    if (p.stride_words > kWsMaxStrideWords) return launch_ks<2>(grid, s, db, sel, partials, p);
+    // the wide selection loads move 16 bytes per lane: rows must start on
+    // 16-byte boundaries; other pitches take the 4-byte loads of the split-K
+    // ring kernel
+    const bool aligned16 = p.stride_words % 4 == 0 && (reinterpret_cast<uintptr_t>(sel) & 15) == 0;
+    if (p.stride_words > kWsMaxStrideWords || !aligned16) return launch_ks<2>(grid, s, db, sel, partials, p);
     const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksw), (int)kWsLdsBytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_stage1_mfma_ksw, grid, dim3(kThreads), kWsLdsBytes, s, db, sel, partials, p);
@@ -1472,6 +1376,32 @@ static hipError_t launch_mfma_t(const Geometry& g, const Plan& pl, const void* d
             hipLaunchKernelGGL((k_stage1_mfma<MT, F4>), grid, dim3(kThreads), 0, s, d, sel, partials, p);
             return hipGetLastError();
     }
+}
+
+template <int MT, bool F4>
+static hipError_t prepare_rings() {
+    hipError_t e = hipSuccess;
+    if ((e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_lds<MT, F4, 2, false>), (int)ring_bytes<MT>(2))) ||
+        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_lds<MT, F4, 3, false>), (int)ring_bytes<MT>(3))) ||
+        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_lds<MT, F4, 4, false>), (int)ring_bytes<MT>(4))) ||
+        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_lds<MT, F4, 6, false>), (int)ring_bytes<MT>(6))))
+        return e;
+    return hipSuccess;
+}
+
+hipError_t prepare_scan_kernels() {
+    hipError_t e = hipSuccess;
+    if ((e = prepare_rings<1, true>()) || (e = prepare_rings<2, true>()) || (e = prepare_rings<4, true>()) ||
+        (e = prepare_rings<1, false>()) || (e = prepare_rings<2, false>()) || (e = prepare_rings<4, false>()))
+        return e;
+    if ((e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_lds<4, true, 3, true>),
+                                (int)(ring_bytes<4>(3) + 16u * 1024u))) ||
+        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ks<2>), (int)ring_bytes<4>(2))) ||
+        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ks<3>), (int)ring_bytes<4>(3))) ||
+        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ks<4>), (int)ring_bytes<4>(4))) ||
+        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksw), (int)kWsLdsBytes)))
+        return e;
+    return hipSuccess;
 }
 
 hipError_t launch_stage1_mfma(const Geometry& g, const Plan& p, const void* db, const uint32_t* sel,

@@ -386,12 +386,18 @@ int Ctx::plan_for(const Db& db, uint32_t q, const pir_kernel_cfg* cfg, Plan& p) 
     return finish_plan(db.geo, q, p);
 }
 
-std::string Ctx::tune_key(const Geometry& g, uint32_t q) const {
+bool TuneKey::operator<(const TuneKey& o) const { return std::tie(R, qb, nbits) < std::tie(o.R, o.qb, o.nbits); }
+
+std::string TuneKey::str(const std::string& arch) const {
+    std::ostringstream os;
+    os << arch << "/R" << R << "/Q" << qb << "/NB" << nbits;
+    return os.str();
+}
+
+TuneKey Ctx::tune_key(const Geometry& g, uint32_t q) const {
     uint32_t nbits = 0;
     while ((1ull << (nbits + 1)) <= g.nb) ++nbits;
-    std::ostringstream os;
-    os << arch << "/R" << g.R << "/Q" << pow2_ceil(q) << "/NB" << nbits;
-    return os.str();
+    return TuneKey{g.R, pow2_ceil(q), nbits};
 }
 
 void Ctx::save_tune_cache() {
@@ -404,7 +410,7 @@ void Ctx::save_tune_cache() {
     for (auto& kv : tuned) {
         if (!first) f << ",\n";
         first = false;
-        f << "  \"" << kv.first << "\": {\"variant\": " << kv.second.variant
+        f << "  \"" << kv.first.str(arch) << "\": {\"variant\": " << kv.second.variant
           << ", \"q_tile\": " << kv.second.q_tile << ", \"unroll\": " << kv.second.unroll
           << ", \"groups\": " << kv.second.groups << "}";
     }
@@ -425,9 +431,13 @@ void Ctx::load_tune_cache() {
         if (b == std::string::npos) continue;
         std::string key = line.substr(a + 1, b - a - 1);
         pir_kernel_cfg c{};
+        TuneKey k{};
+        char arch_buf[32] = {0};
+        if (sscanf(key.c_str(), "%31[^/]/R%u/Q%u/NB%u", arch_buf, &k.R, &k.qb, &k.nbits) != 4 || arch != arch_buf)
+            continue;
         if (sscanf(line.c_str() + b + 1, ": {\"variant\": %u, \"q_tile\": %u, \"unroll\": %u, \"groups\": %u",
                    &c.variant, &c.q_tile, &c.unroll, &c.groups) == 4)
-            tuned[key] = c;
+            tuned[k] = c;
     }
 }
 
@@ -471,6 +481,16 @@ void pack_rows(uint8_t* dst, const uint8_t* src, uint32_t nr, uint64_t src_strid
     pack_range(dst, src, src_stride, row_bytes, dstride, 0, (uint64_t)nr * dstride);
 }
 
+int check_async_args(Db* db, const void* d_sel, uint64_t sel_stride, uint32_t q, void* d_out) {
+    if (!db || !d_sel || !d_out) return fail(PIR_E_INVAL, "NULL argument");
+    if (q == 0 || q > PIR_MAX_BATCH) return fail(PIR_E_INVAL, "q=%u outside [1, %u]", q, PIR_MAX_BATCH);
+    if (sel_stride % 4 != 0 || sel_stride < 4ull * db->geo.nb)
+        return fail(PIR_E_INVAL, "sel_stride %llu must be a multiple of 4 and >= %llu",
+                    (unsigned long long)sel_stride, (unsigned long long)(4ull * db->geo.nb));
+    if (((uintptr_t)d_sel) % 4 != 0) return fail(PIR_E_INVAL, "d_sel must be 4-byte aligned");
+    return PIR_OK;
+}
+
 }  // namespace pir
 
 using namespace pir;
@@ -507,6 +527,8 @@ int pir_ctx_create(int hip_device, pir_ctx** out) {
     if (rc) return rc;
     e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "capture stream");
+    e = prepare_scan_kernels();
+    if (e != hipSuccess) return hip_fail(e, "scan kernel attributes");
     ctx->load_tune_cache();
     *out = reinterpret_cast<pir_ctx*>(ctx.release());
     return PIR_OK;
@@ -678,15 +700,6 @@ uint64_t pir_db_min_sel_stride(const pir_db* d) {
     return 4ull * reinterpret_cast<const Db*>(d)->geo.nb;
 }
 
-static int check_async_args(Db* db, const void* d_sel, uint64_t sel_stride, uint32_t q, void* d_out) {
-    if (!db || !d_sel || !d_out) return fail(PIR_E_INVAL, "NULL argument");
-    if (q == 0 || q > PIR_MAX_BATCH) return fail(PIR_E_INVAL, "q=%u outside [1, %u]", q, PIR_MAX_BATCH);
-    if (sel_stride % 4 != 0 || sel_stride < 4ull * db->geo.nb)
-        return fail(PIR_E_INVAL, "sel_stride %llu must be a multiple of 4 and >= %llu",
-                    (unsigned long long)sel_stride, (unsigned long long)(4ull * db->geo.nb));
-    if (((uintptr_t)d_sel) % 4 != 0) return fail(PIR_E_INVAL, "d_sel must be 4-byte aligned");
-    return PIR_OK;
-}
 
 int pir_dpxor_batch_async_cfg(pir_db* d, const void* d_sel, uint64_t sel_stride, uint32_t q, void* d_out,
                               void* hip_stream, const pir_kernel_cfg* cfg) {

@@ -103,6 +103,15 @@ struct GraphEntry {
     uint64_t last_use = 0;
 };
 
+// Tune-cache key: (record bytes, query-count bucket = Q rounded up to a power
+// of two, log2 of the block count rounded down); the architecture is fixed
+// (gfx950).  A plain struct, so that a lookup allocates nothing.
+struct TuneKey {
+    uint32_t R, qb, nbits;
+    bool operator<(const TuneKey& o) const;
+    std::string str(const std::string& arch) const;  // "gfx950/R32/Q64/NB23" (cache file form)
+};
+
 struct Ctx {
     int device = 0;
     std::string arch;
@@ -111,7 +120,7 @@ struct Ctx {
     std::vector<std::unique_ptr<Exec>> pool;
     std::unordered_map<hipStream_t, DevBuf> workspaces;  // per caller stream
     std::unordered_map<hipStream_t, DpfWs> dpf_ws;       // per caller stream
-    std::map<std::string, pir_kernel_cfg> tuned;
+    std::map<TuneKey, pir_kernel_cfg> tuned;
     std::atomic<bool> timing_on{false};
     std::atomic<bool> graphs_on{true};
     std::mutex graph_mu;                  // guards `graphs`
@@ -138,12 +147,13 @@ struct Ctx {
     int launch_scan(const Db& db, const Plan& p, const uint32_t* d_sel, uint64_t stride_words, uint32_t q,
                     uint8_t* d_out, uint8_t* partials, hipStream_t s);
     void drop_graphs(const void* db);  // all graphs of a database (nullptr: every graph)
-    std::string tune_key(const Geometry& g, uint32_t q) const;
+    TuneKey tune_key(const Geometry& g, uint32_t q) const;
     void save_tune_cache();
     void load_tune_cache();
 };
 
 int finish_plan(const Geometry& g, uint32_t q, Plan& p);
+int check_async_args(Db* db, const void* d_sel, uint64_t sel_stride, uint32_t q, void* d_out);
 
 // DPF evaluation of n_keys device keys into selection rows on stream s, with
 // the stream's node scratch (pir_dpf_api.cpp); and the most scratch that

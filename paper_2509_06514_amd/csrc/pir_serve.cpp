@@ -125,6 +125,7 @@ struct Server {
     pir_serve_config cfg{};
     std::mutex mu;
     std::condition_variable cv_sched, cv_done;
+    std::condition_variable cv_ring;  // a batch retired: ring rows may be free again
     std::vector<std::unique_ptr<DbQueue>> dbs;
     std::vector<std::unique_ptr<Slot>> slots;
     std::unordered_map<uint64_t, Ticket> tickets;
@@ -136,7 +137,7 @@ struct Server {
     // statistics
     std::vector<double> lat_us;
     uint64_t submitted = 0, completed = 0, rejected = 0, batches = 0, h2d_bytes = 0;
-    uint64_t key_requests = 0, updates_applied = 0;
+    uint64_t key_requests = 0, updates_applied = 0, blocked_submits = 0;
     uint64_t hist[13] = {0};
     uint32_t max_inflight = 0;
     Clock::time_point t0;
@@ -170,6 +171,7 @@ void Server::retire(Slot& s, int status) {
     --d.inflight;
     s.reqs.clear();
     s.busy = false;
+    cv_ring.notify_all();
 }
 
 // Upload ring rows [first, first + n) to dst (contiguous modulo the ring size).
@@ -357,6 +359,8 @@ int pir_serve_create(pir_ctx* c, const pir_serve_config* cfg, pir_server** out) 
     if (srv->cfg.n_slots == 0) srv->cfg.n_slots = 4;
     if (srv->cfg.n_slots > 64) return fail(PIR_E_INVAL, "n_slots %u > 64", srv->cfg.n_slots);
     if (srv->cfg.queue_cap == 0) srv->cfg.queue_cap = 65536;
+    if (srv->cfg.submit_wait_ms == 0) srv->cfg.submit_wait_ms = 1000;
+    if (srv->cfg.ring_bytes == 0) srv->cfg.ring_bytes = 256ull << 20;
     int rc = srv->ctx->bind();
     if (rc) return rc;
     for (uint32_t i = 0; i < srv->cfg.n_slots; ++i) {
@@ -411,13 +415,16 @@ int pir_serve_add_db(pir_server* sv, pir_db* d, uint32_t* db_id) {
         return fail(PIR_E_NOMEM, "admitting this database needs %llu bytes; %llu of the %llu-byte budget are taken",
                     (unsigned long long)need, (unsigned long long)srv->admitted_bytes,
                     (unsigned long long)srv->cfg.hbm_budget_bytes);
-    // pinned request rings: selections up to 256 MiB, keys up to 16 MiB; at
-    // least 2 batches each, at most queue_cap rows
-    const uint64_t cap_rows = std::max<uint64_t>(srv->cfg.queue_cap, srv->cfg.q_max);
+    // pinned request rings: ring_bytes of selection rows (default 256 MiB)
+    // and 16 MiB of keys, but at least one batch per slot plus one queued
+    // batch, and no more than can ever be in use (queue_cap queued plus a full
+    // batch in every slot)
+    const uint64_t cap_rows = (uint64_t)srv->cfg.queue_cap + (uint64_t)srv->cfg.n_slots * srv->cfg.q_max;
+    const uint64_t min_rows = (uint64_t)(srv->cfg.n_slots + 1) * srv->cfg.q_max;
     const uint64_t strides[2] = {dq->dstride, dq->key_bytes};
-    const uint64_t budgets[2] = {256ull << 20, 16ull << 20};
+    const uint64_t budgets[2] = {srv->cfg.ring_bytes, 16ull << 20};
     for (int k = 0; k < 2; ++k) {
-        uint64_t rows = std::max<uint64_t>(2ull * srv->cfg.q_max, budgets[k] / strides[k]);
+        uint64_t rows = std::max<uint64_t>(min_rows, budgets[k] / strides[k]);
         rows = std::min<uint64_t>(rows, cap_rows);
         hipError_t e = dq->ring[k].buf.ensure(rows * strides[k]);
         if (e != hipSuccess) return hip_fail(e, "pinned request ring");
@@ -431,11 +438,16 @@ int pir_serve_add_db(pir_server* sv, pir_db* d, uint32_t* db_id) {
     return PIR_OK;
 }
 
-int pir_serve_submit(pir_server* sv, uint32_t db_id, const uint8_t* sel_bits, uint8_t* out, uint64_t* ticket) {
-    clear_error();
-    if (!sv || !sel_bits || !out || !ticket) return fail(PIR_E_INVAL, "pir_serve_submit: NULL argument");
-    Server* srv = reinterpret_cast<Server*>(sv);
-    std::unique_lock<std::mutex> lk(srv->mu);
+}  // extern "C"
+
+namespace pir {
+
+// Admission of one request of kind k into database db_id's queue (mu held).
+// PIR_E_BUSY only when the database's queue holds queue_cap requests; when
+// the queue has room but the pinned ring has no free row (every row belongs
+// to a queued or in-flight request), the caller waits for a batch to retire,
+// at most submit_wait_ms, before PIR_E_BUSY.
+static int admit(Server* srv, std::unique_lock<std::mutex>& lk, uint32_t db_id, int k, DbQueue** out) {
     if (srv->stopping) {
         ++srv->rejected;
         return fail(PIR_E_SHUTDOWN, "server is shutting down");
@@ -443,10 +455,47 @@ int pir_serve_submit(pir_server* sv, uint32_t db_id, const uint8_t* sel_bits, ui
     if (srv->failed) return fail(PIR_E_DEVICE, "server stopped after a device error");
     if (db_id >= srv->dbs.size()) return fail(PIR_E_NOTFOUND, "unknown database id %u", db_id);
     DbQueue& d = *srv->dbs[db_id];
-    if (d.q[kSel].size() >= srv->cfg.queue_cap || d.ring[kSel].free_rows() == 0) {
+    if (d.q[k].size() >= srv->cfg.queue_cap) {
         ++srv->rejected;
-        return fail(PIR_E_BUSY, "queue of database %u is full", db_id);
+        return fail(PIR_E_BUSY, "%s queue of database %u holds queue_cap = %u requests", k == kSel ? "selection" : "key",
+                    db_id, srv->cfg.queue_cap);
     }
+    if (d.ring[k].free_rows() == 0) {
+        ++srv->blocked_submits;
+        const auto until = Clock::now() + std::chrono::milliseconds(srv->cfg.submit_wait_ms);
+        srv->cv_ring.wait_until(lk, until, [&] { return d.ring[k].free_rows() > 0 || srv->stopping || srv->failed; });
+        if (srv->stopping) {
+            ++srv->rejected;
+            return fail(PIR_E_SHUTDOWN, "server is shutting down");
+        }
+        if (srv->failed) return fail(PIR_E_DEVICE, "server stopped after a device error");
+        if (d.ring[k].free_rows() == 0) {
+            ++srv->rejected;
+            return fail(PIR_E_BUSY, "no pinned ring row of database %u freed within %u ms", db_id,
+                        srv->cfg.submit_wait_ms);
+        }
+        if (d.q[k].size() >= srv->cfg.queue_cap) {
+            ++srv->rejected;
+            return fail(PIR_E_BUSY, "queue of database %u holds queue_cap = %u requests", db_id, srv->cfg.queue_cap);
+        }
+    }
+    *out = &d;
+    return PIR_OK;
+}
+
+}  // namespace pir
+
+extern "C" {
+
+int pir_serve_submit(pir_server* sv, uint32_t db_id, const uint8_t* sel_bits, uint8_t* out, uint64_t* ticket) {
+    clear_error();
+    if (!sv || !sel_bits || !out || !ticket) return fail(PIR_E_INVAL, "pir_serve_submit: NULL argument");
+    Server* srv = reinterpret_cast<Server*>(sv);
+    std::unique_lock<std::mutex> lk(srv->mu);
+    DbQueue* dp = nullptr;
+    const int rc = admit(srv, lk, db_id, kSel, &dp);
+    if (rc) return rc;
+    DbQueue& d = *dp;
     const uint64_t row = d.ring[kSel].next_row++;
     memcpy(d.ring[kSel].row_ptr(row), sel_bits, d.row_bytes);
     const uint64_t t = srv->new_ticket();
@@ -463,17 +512,10 @@ int pir_serve_submit_key(pir_server* sv, uint32_t db_id, const uint8_t* key, uin
     if (!sv || !key || !out || !ticket) return fail(PIR_E_INVAL, "pir_serve_submit_key: NULL argument");
     Server* srv = reinterpret_cast<Server*>(sv);
     std::unique_lock<std::mutex> lk(srv->mu);
-    if (srv->stopping) {
-        ++srv->rejected;
-        return fail(PIR_E_SHUTDOWN, "server is shutting down");
-    }
-    if (srv->failed) return fail(PIR_E_DEVICE, "server stopped after a device error");
-    if (db_id >= srv->dbs.size()) return fail(PIR_E_NOTFOUND, "unknown database id %u", db_id);
-    DbQueue& d = *srv->dbs[db_id];
-    if (d.q[kKey].size() >= srv->cfg.queue_cap || d.ring[kKey].free_rows() == 0) {
-        ++srv->rejected;
-        return fail(PIR_E_BUSY, "key queue of database %u is full", db_id);
-    }
+    DbQueue* dp = nullptr;
+    const int rc = admit(srv, lk, db_id, kKey, &dp);
+    if (rc) return rc;
+    DbQueue& d = *dp;
     const uint64_t row = d.ring[kKey].next_row++;
     memcpy(d.ring[kKey].row_ptr(row), key, d.key_bytes);
     const uint64_t t = srv->new_ticket();
@@ -561,6 +603,7 @@ int pir_serve_stats_get(pir_server* sv, pir_serve_stats* out, int reset) {
     out->n_slots = (uint32_t)srv->slots.size();
     out->key_requests = srv->key_requests;
     out->updates_applied = srv->updates_applied;
+    out->blocked_submits = srv->blocked_submits;
     out->elapsed_s = std::chrono::duration<double>(Clock::now() - srv->t0).count();
     out->qps = out->elapsed_s > 0 ? (double)srv->completed / out->elapsed_s : 0.0;
     if (!srv->lat_us.empty()) {
@@ -583,7 +626,7 @@ int pir_serve_stats_get(pir_server* sv, pir_serve_stats* out, int reset) {
     if (reset) {
         srv->lat_us.clear();
         srv->submitted = srv->completed = srv->rejected = srv->batches = srv->h2d_bytes = 0;
-        srv->key_requests = srv->updates_applied = 0;
+        srv->key_requests = srv->updates_applied = srv->blocked_submits = 0;
         for (auto& h : srv->hist) h = 0;
         srv->max_inflight = 0;
         srv->t0 = Clock::now();
@@ -600,6 +643,7 @@ int pir_serve_destroy(pir_server* sv) {
         srv->stopping = true;
     }
     srv->cv_sched.notify_all();
+    srv->cv_ring.notify_all();
     if (srv->th.joinable()) srv->th.join();
     (void)srv->ctx->bind();
     for (auto& s : srv->slots) {

@@ -71,3 +71,30 @@ def test_no_device_fails_loudly():
     rc = lib.pir_ctx_create(0, ctypes.byref(h))
     assert rc == _native.PIR_E_DEVICE
     assert lib.pir_last_error()
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # the ctypes mirrors have the size and field offsets of the C structs in
+    # include/pir.h, as gcc lays them out
+    import subprocess
+    structs = {"pir_db_info": _native.pir_db_info, "pir_kernel_cfg": _native.pir_kernel_cfg,
+               "pir_timing": _native.pir_timing, "pir_serve_config": _native.pir_serve_config,
+               "pir_serve_stats": _native.pir_serve_stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pir.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} sizeof %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines.append("  return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", f"-I{os.path.join(ROOT, 'include')}", str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        name, field, val = line.split()
+        got[(name, field)] = int(val)
+    for name, cls in structs.items():
+        assert got[(name, "sizeof")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)

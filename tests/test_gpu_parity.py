@@ -192,6 +192,16 @@ def test_invalid_arguments(ctx):
 MFMA_VARIANTS = [pir.PIR_VARIANT_MFMA_F4, pir.PIR_VARIANT_MFMA_I8]
 
 
+def _mfma_cfg_exists(variant, qt, unroll):
+    """The matrix-core (q_tile, unroll) combinations the library compiles."""
+    f4 = variant == pir.PIR_VARIANT_MFMA_F4
+    if unroll in (1, 2, 3, 4, 6):
+        return qt in (16, 32, 64)
+    if unroll in (7, 12, 13, 14, 15):
+        return f4 and qt == 64
+    return False
+
+
 @pytest.mark.parametrize("variant", MFMA_VARIANTS)
 @pytest.mark.parametrize("n,r", [(50000, 32), (4099, 64), (3333, 256), (1000, 1024), (70001, 128), (31, 32)])
 def test_mfma_variants(ctx, variant, n, r):
@@ -208,7 +218,7 @@ def test_mfma_variants(ctx, variant, n, r):
             # registers, LDS rings of 2/3/4/6 stages, shared spread, split K on 2/3/4
             # stages, split K with selection words 4 K-steps at a time
             for unroll in (1, 2, 3, 4, 6, 7, 12, 13, 14, 15):
-                if unroll >= 7 and not (variant == pir.PIR_VARIANT_MFMA_F4 and qt == 64):
+                if not _mfma_cfg_exists(variant, qt, unroll):
                     continue
                 for groups in (0, 3, 1):
                     d_out.fill_(0xEE)
@@ -294,4 +304,41 @@ def test_host_path_pinned_and_staged(ctx):
     p_one = pir.pinned_empty((r,))
     assert np.array_equal(db.dpxor(p_sel[3], out=p_one), want[3])
     assert np.array_equal(db.dpxor(sel[7]), want[7])
+    db.free()
+
+
+@pytest.mark.parametrize("n,r", [(50000, 32), (3333, 256)])
+def test_wide_selection_kernel_unaligned_rows(ctx, n, r):
+    # The split-K kernel with wide selection reads moves 16 bytes of a row per
+    # lane.  At the minimum pitch (4 * ceil(N/32) bytes, not a multiple of 16
+    # here) and at a base 4 bytes past an aligned address the launcher must
+    # take the 4-byte selection loads instead; the answers stay the oracle's.
+    dbh = synth.database(n, r, seed=0x16A + n + r)
+    db = ctx.load_db(dbh)
+    stride = db.min_sel_stride
+    assert stride % 16 != 0
+    q = 64
+    sel = synth.selections(n, q, seed=0x16B + n, stride=stride)
+    want = oracle.dpxor_batch(dbh, sel)
+    cfgs = [pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 15, 0)]
+    d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
+    for cfg in cfgs:
+        for base in (0, 4):
+            buf = torch.zeros(q * stride + 16, dtype=torch.uint8, device="cuda:0")
+            buf[base:base + q * stride] = torch.from_numpy(sel.reshape(-1))
+            d_sel = buf[base:]
+            for qq in (q, 5):
+                d_out.fill_(0xEE)
+                db.dpxor_batch_async(d_sel, qq, d_out, sel_stride=stride, cfg=cfg)
+                torch.cuda.synchronize()
+                assert np.array_equal(d_out.cpu().numpy()[:qq], want[:qq]), (cfg, base, qq)
+    cfg = cfgs[0]
+    # an aligned pitch (a multiple of 16 bytes) on the same rows
+    stride16 = (stride + 15) // 16 * 16
+    rows = np.zeros((q, stride16), np.uint8)
+    rows[:, :stride] = sel
+    d_out.fill_(0xEE)
+    db.dpxor_batch_async(torch.from_numpy(rows).to("cuda:0"), q, d_out, sel_stride=stride16, cfg=cfg)
+    torch.cuda.synchronize()
+    assert np.array_equal(d_out.cpu().numpy(), want)
     db.free()

@@ -148,3 +148,92 @@ def test_poll_interface(ctx, three_dbs):
     assert done and st == _native.PIR_OK
     assert np.array_equal(out, oracle.dpxor(hosts[0], sel))
     srv.close()
+
+
+# The serving configuration at its stated sizes: three resident databases of
+# 2^23 x 32 B, 2^24 x 128 B and 2^22 x 1024 B (0.25, 2 and 4 GiB).
+C5_SHAPES = [(1 << 23, 32), (1 << 24, 128), (1 << 22, 1024)]
+C5_POOL = 64  # distinct selection vectors per database
+
+
+@pytest.fixture(scope="module")
+def c5(ctx):
+    hosts, dbs, pools, wants = [], [], [], []
+    for k, (n, r) in enumerate(C5_SHAPES):
+        h = synth.database(n, r, seed=synth.S_DB + 5 + k)
+        hosts.append(h)
+        dbs.append(ctx.load_db(h))
+        pool = synth.selections(n, C5_POOL, seed=synth.S_SEL + 60 + k)
+        pools.append(pool)
+        wants.append(oracle.dpxor_rows(h, pool))  # every pool row, answered alone by the oracle
+    yield hosts, dbs, pools, wants
+    for d in dbs:
+        d.free()
+
+
+def test_c5_poisson_mix_matches_oracle(ctx, c5):
+    # Open-loop Poisson arrivals (8k q/s offered from 4 threads), each request
+    # to a database drawn uniformly: every answer in the mix equals the
+    # oracle's answer to that selection alone, batches form and overlap, and
+    # no request is turned away.
+    import time
+
+    hosts, dbs, pools, wants = c5
+    srv = pir.Server(ctx, q_max=64, max_wait_us=200, n_slots=4, queue_cap=1 << 20)
+    ids = [srv.add_db(d) for d in dbs]
+    rate, seconds, n_thr = 8000.0, 0.6, 4
+    records = [[] for _ in range(n_thr)]  # (ticket, db, pool row, out)
+
+    def submitter(tid):
+        rng = np.random.default_rng(0xC5 + tid)
+        t = time.perf_counter()
+        stop = t + seconds
+        while True:
+            t += rng.exponential(n_thr / rate)
+            if t > stop:
+                break
+            dt = t - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            w = int(rng.integers(0, 3))
+            k = int(rng.integers(0, C5_POOL))
+            out = np.zeros(C5_SHAPES[w][1], np.uint8)
+            rc, tk = srv.submit_raw(ids[w], pools[w][k].ctypes.data, out.ctypes.data)
+            records[tid].append((rc, tk, w, k, out))
+
+    ths = [threading.Thread(target=submitter, args=(i,)) for i in range(n_thr)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    done = [r for lst in records for r in lst]
+    assert all(rc == _native.PIR_OK for rc, *_ in done), "a submit was refused"
+    for rc, tk, w, k, out in done:
+        assert srv.wait(tk, 60000) == _native.PIR_OK
+    st = srv.stats()
+    srv.close()
+    bad = [(w, k) for rc, tk, w, k, out in done if not np.array_equal(out, wants[w][k])]
+    assert not bad, f"{len(bad)} of {len(done)} answers differ from the oracle, first {bad[:5]}"
+    assert len(done) > 2000
+    assert st["completed"] == len(done) and st["rejected"] == 0
+    assert st["batches"] < len(done), "requests were coalesced into batches"
+    assert st["max_inflight"] >= 2, "batches overlapped on the device"
+
+
+def test_full_ring_blocks_instead_of_rejecting(ctx, c5):
+    # One slot, single-request batches and the smallest ring ((n_slots + 1) *
+    # q_max = 2 rows) on the 4 GiB database: submits wait for a batch to retire
+    # instead of failing, and every answer is exact.
+    hosts, dbs, pools, wants = c5
+    srv = pir.Server(ctx, q_max=1, max_wait_us=0, n_slots=1, queue_cap=1000, ring_bytes=1)
+    i = srv.add_db(dbs[2])
+    outs = [np.zeros(C5_SHAPES[2][1], np.uint8) for _ in range(24)]
+    tickets = [srv.submit(i, pools[2][k], outs[k]) for k in range(24)]
+    for t in tickets:
+        assert srv.wait(t, 60000) == _native.PIR_OK
+    st = srv.stats()
+    srv.close()
+    for k in range(24):
+        assert np.array_equal(outs[k], wants[2][k]), k
+    assert st["rejected"] == 0
+    assert st["blocked_submits"] > 0, "the two-row ring never filled"
