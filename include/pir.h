@@ -148,6 +148,29 @@ int pir_dpxor_batch(pir_db* db, const uint8_t* sel_bits, uint64_t sel_stride, ui
 int pir_dpxor_batch_async(pir_db* db, const void* d_sel, uint64_t sel_stride, uint32_t q,
                           void* d_out, void* hip_stream);
 
+/*
+ * The same scan for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation).  Same
+ * arguments, layout and results as pir_dpxor_batch_async; the partial
+ * answers go to a fixed per-device scratch array of
+ * PIR_NOALLOC_SCRATCH_BYTES bytes that the library holds on every GPU it
+ * runs on until the process ends (its address is looked up when a context
+ * is created on the device), instead of a library-allocated workspace.  The
+ * call allocates nothing, records no events and captures no graph: it
+ * enqueues the scan's two kernels on hip_stream.  When the plan's partials
+ * (record groups x q x R rounded up to 4 bytes) exceed the scratch, the
+ * records are taken in fewer, longer groups (same answers); if even the
+ * fewest groups the exact matrix-core counts allow do not fit (about
+ * q * R > 32 MiB), the call fails with PIR_E_INVAL and a message naming the
+ * limit.  Every call on a GPU uses that GPU's one array: calls that overlap
+ * on the device (on other streams, or from other host threads without
+ * ordering) race on it and must not be issued; calls on one stream are
+ * ordered and safe.  Nothing in the array needs clearing between calls.
+ */
+#define PIR_NOALLOC_SCRATCH_BYTES (32u << 20)
+int pir_dpxor_batch_async_noalloc(pir_db* db, const void* d_sel, uint64_t sel_stride, uint32_t q, void* d_out,
+                                  void* hip_stream);
+
 /* Explicit kernel configuration (tests of tile invariance, the autotuner). */
 typedef struct pir_kernel_cfg {
     uint32_t variant; /* PIR_VARIANT_* */

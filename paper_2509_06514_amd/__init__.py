@@ -290,6 +290,21 @@ class Database:
                                                  ctypes.c_void_p(d_out.data_ptr()), s, ctypes.byref(c))
         check(rc, "pir_dpxor_batch_async")
 
+    def dpxor_batch_async_noalloc(self, d_sel, q, d_out, sel_stride=None, stream=None):
+        """As dpxor_batch_async, with the partial answers in the library's fixed
+        per-device scratch (no allocation; calls that overlap on one GPU race)."""
+        if sel_stride is None:
+            sel_stride = d_sel.stride(0) * d_sel.element_size() if d_sel.dim() == 2 else self.min_sel_stride
+        if d_sel.device.type != "cuda" or d_out.device.type != "cuda":
+            raise ValueError("device tensors required")
+        if d_sel.numel() * d_sel.element_size() < (q - 1) * sel_stride + self.min_sel_stride:
+            raise ValueError("d_sel too small")
+        if d_out.numel() * d_out.element_size() < q * self.record_bytes:
+            raise ValueError("d_out too small")
+        check(lib().pir_dpxor_batch_async_noalloc(self._h, ctypes.c_void_p(d_sel.data_ptr()), sel_stride, q,
+                                                  ctypes.c_void_p(d_out.data_ptr()), _stream_handle(stream)),
+              "pir_dpxor_batch_async_noalloc")
+
     def dpf_dpxor_async(self, d_keys, n_keys, d_out, stream=None, fused=False):
         """Answers from DPF keys: row q of d_out = XOR_j Eval(k_q, j) * D[j] (device tensors).
         fused: the evaluation's last level and the scan in one kernel (pir_dpf_dpxor_fused_async)."""

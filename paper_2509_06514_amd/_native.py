@@ -68,6 +68,8 @@ class pir_serve_stats(ctypes.Structure):
                 ("blocked_submits", ctypes.c_uint64)]
 
 
+PIR_NOALLOC_SCRATCH_BYTES = 32 << 20  # fixed scratch of pir_dpxor_batch_async_noalloc, per device
+
 _P = ctypes.c_void_p
 _PP = ctypes.POINTER(ctypes.c_void_p)
 _U64 = ctypes.c_uint64
@@ -90,6 +92,7 @@ SIGNATURES = {
     "pir_dpxor_batch": (_I, [_P, _P, _U64, _U32, _P]),
     "pir_dpxor_batch_async": (_I, [_P, _P, _U64, _U32, _P, _P]),
     "pir_dpxor_batch_async_cfg": (_I, [_P, _P, _U64, _U32, _P, _P, ctypes.POINTER(pir_kernel_cfg)]),
+    "pir_dpxor_batch_async_noalloc": (_I, [_P, _P, _U64, _U32, _P, _P]),
     "pir_get_cfg": (_I, [_P, _U32, ctypes.POINTER(pir_kernel_cfg)]),
     "pir_tune": (_I, [_P, _U32, ctypes.POINTER(pir_kernel_cfg)]),
     "pir_graphs_enable": (_I, [_P, _I]),

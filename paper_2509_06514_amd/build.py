@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpir.so")
 ARCH = "gfx950"
 
-SOURCES = ["pir_kernels.hip", "pir_dpf.hip", "pir_fp.hip", "pir_probe.hip",
+SOURCES = ["pir_kernels.hip", "pir_dpf.hip", "pir_fp.hip", "pir_probe.hip", "pir_noalloc.hip",
            "pir_runtime.cpp", "pir_dpf_api.cpp", "pir_fp_api.cpp", "pir_serve.cpp"]
 
 # Sources whose matrix-core accumulators may live in the accumulation

@@ -529,6 +529,9 @@ int pir_ctx_create(int hip_device, pir_ctx** out) {
     if (e != hipSuccess) return hip_fail(e, "capture stream");
     e = prepare_scan_kernels();
     if (e != hipSuccess) return hip_fail(e, "scan kernel attributes");
+    // the no-allocation entry point's fixed scratch on this device
+    rc = noalloc_scratch_for_current_device(&ctx->noalloc_scratch);
+    if (rc) return rc;
     ctx->load_tune_cache();
     *out = reinterpret_cast<pir_ctx*>(ctx.release());
     return PIR_OK;

@@ -121,6 +121,7 @@ struct Ctx {
     std::unordered_map<hipStream_t, DevBuf> workspaces;  // per caller stream
     std::unordered_map<hipStream_t, DpfWs> dpf_ws;       // per caller stream
     std::map<TuneKey, pir_kernel_cfg> tuned;
+    void* noalloc_scratch = nullptr;  // this device's fixed scan scratch (pir_noalloc.hip)
     std::atomic<bool> timing_on{false};
     std::atomic<bool> graphs_on{true};
     std::mutex graph_mu;                  // guards `graphs`
@@ -154,6 +155,10 @@ struct Ctx {
 
 int finish_plan(const Geometry& g, uint32_t q, Plan& p);
 int check_async_args(Db* db, const void* d_sel, uint64_t sel_stride, uint32_t q, void* d_out);
+
+// The fixed scan scratch of the no-allocation entry point (pir_noalloc.hip):
+// its device address on the current device, looked up once per device.
+int noalloc_scratch_for_current_device(void** out);
 
 // DPF evaluation of n_keys device keys into selection rows on stream s, with
 // the stream's node scratch (pir_dpf_api.cpp); and the most scratch that
