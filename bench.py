@@ -88,15 +88,13 @@ def kernel_name(cfg, r):
         return f"k_stage1_valu<{cfg.q_tile}, {cfg.unroll}, {'true' if r < 32 else 'false'}>"
     mt = cfg.q_tile // 16
     f4 = "true" if cfg.variant == 3 else "false"
-    if cfg.unroll in (2, 3, 4, 6):  # LDS ring of that many stages
-        return f"k_stage1_mfma_lds<{mt}, {f4}, {cfg.unroll}, false>"
-    if cfg.unroll == 7:  # 3-stage ring, selection operand spread once per workgroup
-        return f"k_stage1_mfma_lds<{mt}, {f4}, 3, true>"
-    if 12 <= cfg.unroll <= 14:  # split K on a ring of 2/3/4 stages
-        return f"k_stage1_mfma_ks<{cfg.unroll - 10}>"
+    if cfg.unroll in (2, 3, 4):  # LDS ring of that many stages
+        return f"k_stage1_mfma_lds<{mt}, {f4}, {cfg.unroll}>"
+    if cfg.unroll == 12:  # split K on a 2-stage ring
+        return "k_stage1_mfma_ks<2>"
     if cfg.unroll == 15:  # split K, 2-stage ring, selection words 4 K-steps at a time
         return "k_stage1_mfma_ksw"
-    return f"k_stage1_mfma<{mt}, {f4}>"
+    return None
 
 
 def load_traffic(n, r, q, cfg):
@@ -310,7 +308,7 @@ def variant_sweep(ctx, db, d_sel, stride, n, r, q, d_out, torch, pir, reps=3):
         for v in (2, 3):
             for qt in (16, 32, 64):
                 if qt <= max(p2, 16):
-                    fams[v] += [(qt, u) for u in (2, 3, 4) + ((12, 13, 14, 15) if v == 3 and qt == 64 else ())]
+                    fams[v] += [(qt, u) for u in (2, 3, 4) + ((15,) if v == 3 and qt == 64 else ())]
     ref, same, out = None, True, {}
     for v, cands in fams.items():
         best = None
@@ -441,21 +439,6 @@ def dpf_bench(ctx, db, db_host, n, r, args, torch, pir):
                             "ms_per_call": wall_a / args.dpf_steps * 1e3, "two_server_check": bool(ok_a)}
     log(f"keys -> answers: {out['key_to_answer']['queries_per_s']:.1f} q/s, two-server check {ok_a}")
 
-    # the same with the last tree level and the scan in one kernel
-    d_fused = torch.empty((nk, r), dtype=torch.uint8, device="cuda:0")
-
-    def step_fused():
-        db.dpf_dpxor_async(d_keys, nk, d_fused, fused=True)
-
-    step_fused()
-    torch.cuda.synchronize()
-    wall_f, _ = time_steps(step_fused, args.dpf_steps, torch)
-    fused = d_fused.cpu().numpy()
-    out["key_to_answer_fused"] = {"queries_per_s": nk * args.dpf_steps / wall_f,
-                                  "ms_per_call": wall_f / args.dpf_steps * 1e3,
-                                  "same_as_pipeline": bool(np.array_equal(fused, ans))}
-    log(f"keys -> answers, fused: {out['key_to_answer_fused']['queries_per_s']:.1f} q/s, "
-        f"same as the pipeline {out['key_to_answer_fused']['same_as_pipeline']}")
     if args.cpu_sample > 0:
         out["cpu_baseline"] = dpf_cpu_baseline(keys[0])
     return out

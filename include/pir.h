@@ -175,13 +175,10 @@ int pir_dpxor_batch_async_noalloc(pir_db* db, const void* d_sel, uint64_t sel_st
 typedef struct pir_kernel_cfg {
     uint32_t variant; /* PIR_VARIANT_* */
     uint32_t q_tile;  /* queries per workgroup tile (variant-specific; 0 = default) */
-    uint32_t unroll;  /* VALU: blocks per wave iteration; MFMA: 1 = register pipeline,
-                         2/3/4/6 = LDS ring of that many stages, 7 = 3-stage ring with the
-                         selection operand spread once per workgroup (fp4, q_tile 64),
-                         12/13/14 = split-K kernel on a ring of 2/3/4 stages (fp4,
-                         q_tile 64), 15 = split-K kernel on a 2-stage ring whose
-                         selection words arrive 4 K-steps at a time (fp4, q_tile 64);
-                         0 = default */
+    uint32_t unroll;  /* VALU: blocks per wave iteration; MFMA: 2/3/4 = LDS ring of that
+                         many stages, 12 = split-K kernel on a 2-stage ring (fp4, q_tile 64),
+                         15 = split-K kernel on a 2-stage ring whose selection words arrive
+                         4 K-steps at a time (fp4, q_tile 64); 0 = default */
     uint32_t groups;  /* record groups = partial results per query (0 = default) */
 } pir_kernel_cfg;
 
@@ -401,18 +398,6 @@ int pir_dpf_eval_async(pir_ctx* ctx, const void* d_keys, uint32_t n, uint32_t n_
  * asynchronous on hip_stream, with the same workspace rules.
  */
 int pir_dpf_dpxor_async(pir_db* db, const void* d_keys, uint32_t n_keys, void* d_out, void* hip_stream);
-
-/*
- * The same answers with the evaluation's last level and the scan in one
- * kernel (Sec. 3.2 then Sec. 3.3, the leaves consumed where they are made):
- * each thread expands the 32 leaves of one 32-record block and the wave
- * applies them to its 64 blocks of the database at once, so no selection
- * bits are written to or read from memory.  The database is read once per
- * key (the batched scan of pir_dpf_dpxor_async reads it once per 64 keys).
- * Same arguments, layout and workspace rules as pir_dpf_dpxor_async;
- * record_bytes must be at most 4096 (PIR_E_INVAL otherwise).
- */
-int pir_dpf_dpxor_fused_async(pir_db* db, const void* d_keys, uint32_t n_keys, void* d_out, void* hip_stream);
 
 /*
  * Client side, host only: the record from the two servers' answers

@@ -305,9 +305,8 @@ class Database:
                                                   ctypes.c_void_p(d_out.data_ptr()), _stream_handle(stream)),
               "pir_dpxor_batch_async_noalloc")
 
-    def dpf_dpxor_async(self, d_keys, n_keys, d_out, stream=None, fused=False):
-        """Answers from DPF keys: row q of d_out = XOR_j Eval(k_q, j) * D[j] (device tensors).
-        fused: the evaluation's last level and the scan in one kernel (pir_dpf_dpxor_fused_async)."""
+    def dpf_dpxor_async(self, d_keys, n_keys, d_out, stream=None):
+        """Answers from DPF keys: row q of d_out = XOR_j Eval(k_q, j) * D[j] (device tensors)."""
         n = dpf_domain_bits(self.n_records)
         if d_keys.device.type != "cuda" or d_out.device.type != "cuda":
             raise ValueError("device tensors required")
@@ -315,9 +314,9 @@ class Database:
             raise ValueError("d_keys too small")
         if d_out.numel() * d_out.element_size() < n_keys * self.record_bytes:
             raise ValueError("d_out too small")
-        name = "pir_dpf_dpxor_fused_async" if fused else "pir_dpf_dpxor_async"
-        check(getattr(lib(), name)(self._h, ctypes.c_void_p(d_keys.data_ptr()), n_keys,
-                                   ctypes.c_void_p(d_out.data_ptr()), _stream_handle(stream)), name)
+        check(lib().pir_dpf_dpxor_async(self._h, ctypes.c_void_p(d_keys.data_ptr()), n_keys,
+                                        ctypes.c_void_p(d_out.data_ptr()), _stream_handle(stream)),
+              "pir_dpf_dpxor_async")
 
     def get_cfg(self, q):
         c = _native.pir_kernel_cfg()

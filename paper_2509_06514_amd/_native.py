@@ -112,7 +112,6 @@ SIGNATURES = {
     "pir_dpf_gen": (_I, [_U64, _U32, _P, _P, _P, _P]),
     "pir_dpf_eval_async": (_I, [_P, _P, _U32, _U32, _U64, _P, _U64, _P]),
     "pir_dpf_dpxor_async": (_I, [_P, _P, _U32, _P, _P]),
-    "pir_dpf_dpxor_fused_async": (_I, [_P, _P, _U32, _P, _P]),
     "pir_reconstruct": (_I, [_P, _P, _U64, _P]),
     "pir_fp_db_load": (_I, [_P, _P, _U64, _U32, _U32, _PP]),
     "pir_fp_db_free": (_I, [_P]),

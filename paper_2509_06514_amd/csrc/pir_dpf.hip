@@ -374,99 +374,6 @@ k_dpf_expand(const uint8_t* __restrict__ keys, uint32_t key_bytes, uint32_t n, u
     if (BITS) out_bits[q * bits_stride + i] = word;
 }
 
-// The last level fused with the scan (the selection bits never leave the
-// registers).  A workgroup takes one key and one range of BS blocks; thread
-// i of the range expands its node of level a = n - E into the 32 leaf bits
-// of block i, which are block i's selection word for the key.
-// Right after its own walk (its neighbours may still be walking, so the
-// database reads of one wave overlap the AES work of the others), each wave
-// scans its 64 consecutive blocks of the bit-sliced database (db: 16-byte
-// chunks, cpb per block, blocks contiguous): lane l takes chunks l, l + 64,
-// ... of every block, each block's selection word broadcast from its lane,
-// and XOR-accumulates the selected words (the select-XOR of the vector-ALU
-// scan).  The parity of a chunk word's accumulator is one answer bit; chunks
-// 2m and 2m+1 make byte m.  The waves' R-byte results meet in LDS, and the
-// workgroup XORs its rpad/4 words into slot (range % kDpfScanSlots) of
-// `acc` ([slot][key][rpad / 4], zeroed beforehand) with global atomics,
-// which the cross-workgroup reduction then folds.  Blocks past count
-// contribute nothing.  Dynamic LDS: the lookup table at address 0 (the
-// kernel has no static LDS), then (BS / 64) rows of rpad bytes.
-template <int BS>
-__global__ void __launch_bounds__(BS)
-k_dpf_scan(const uint8_t* __restrict__ keys, uint32_t key_bytes, uint32_t n, uint32_t a, uint32_t E,
-           uint64_t count, const u32x4* __restrict__ in, uint64_t in_stride, const u32x4* __restrict__ db,
-           uint32_t cpb, uint32_t R, uint32_t rpad, uint32_t n_keys, uint32_t ranges, uint32_t* __restrict__ acc_out) {
-    extern __shared__ __attribute__((aligned(16))) uint32_t dpf_scan_lds[];
-    uint32_t* const s_tab = dpf_scan_lds;
-    uint8_t* const red = reinterpret_cast<uint8_t*>(dpf_scan_lds + kTabBytes / 4);  // [wave][rpad]
-    // Workgroup v = range * n_keys + key, numbered XCD-major (consecutive v on
-    // one XCD): the keys of one block range run side by side and read the
-    // range's database tile through the same L2.
-    const uint32_t total = ranges * n_keys;
-    const uint32_t per_xcd = (total + 7) / 8;
-    const uint32_t v = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    if (v >= total) return;  // grid padding (whole workgroup)
-    const uint32_t q = v % n_keys, range = v / n_keys;
-    stage_table<BS>(s_tab);
-    const uint64_t i = (uint64_t)range * BS + threadIdx.x;
-    const u32x4* kq = reinterpret_cast<const u32x4*>(keys + (uint64_t)q * key_bytes);
-    const Lut L{s_tab, (threadIdx.x & 31u) * 4u, 128u + (threadIdx.x & 31u) * 4u};
-    uint32_t word = 0;
-    if (i < count) {
-        const u32x4 cur = (a == 0) ? kq[0] : in[q * in_stride + i];
-        word = dfs_expand<true>(L, kq, n + 1, a, E, cur, nullptr);
-    }
-    const uint32_t s = nib_swap02(word);  // stored order
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint64_t i0 = (uint64_t)range * BS + 64u * wave;  // the wave's first block
-    const uint32_t nblk = i0 < count ? (count - i0 < 64 ? (uint32_t)(count - i0) : 64u) : 0u;
-    for (uint32_t k0 = 0; k0 < cpb; k0 += 64) {
-        const uint32_t k = k0 + lane;
-        u32x4 acc = u32x4{0, 0, 0, 0};
-        if (k < cpb) {
-            // eight blocks' loads in flight at a time; past nblk a load
-            // repeats the last block and its selection word is zero
-            const u32x4* src = db + i0 * cpb + k;
-            for (uint32_t b0 = 0; b0 < nblk; b0 += 8) {
-                u32x4 d[8];
-#pragma unroll
-                for (uint32_t u = 0; u < 8; ++u) {
-                    const uint32_t bb = b0 + u < nblk ? b0 + u : nblk - 1;
-                    d[u] = __builtin_nontemporal_load(src + (uint64_t)bb * cpb);
-                }
-#pragma unroll
-                for (uint32_t u = 0; u < 8; ++u) {
-                    const uint32_t sb = b0 + u < nblk ? __builtin_amdgcn_readlane(s, b0 + u) : 0u;
-                    acc.x ^= d[u].x & sb;
-                    acc.y ^= d[u].y & sb;
-                    acc.z ^= d[u].z & sb;
-                    acc.w ^= d[u].w & sb;
-                }
-            }
-        }
-        const uint32_t nib = (__builtin_popcount(acc.x) & 1u) | ((__builtin_popcount(acc.y) & 1u) << 1) |
-                             ((__builtin_popcount(acc.z) & 1u) << 2) | ((__builtin_popcount(acc.w) & 1u) << 3);
-        const uint32_t other = (uint32_t)__shfl_xor((int)nib, 1);
-        if (k < cpb && (k & 1u) == 0) red[wave * rpad + (k >> 1)] = (uint8_t)(nib | (other << 4));
-    }
-    if (lane < rpad - R) red[wave * rpad + R + lane] = 0;  // row padding
-    __syncthreads();
-    const uint32_t words = rpad / 4;
-    uint32_t* const dst = acc_out + ((uint64_t)(range % kDpfScanSlots) * n_keys + q) * words;
-    for (uint32_t w = threadIdx.x; w < words; w += BS) {
-        uint32_t x = 0;
-        for (uint32_t v = 0; v < BS / 64; ++v) x ^= reinterpret_cast<const uint32_t*>(red + v * rpad)[w];
-        atomicXor(dst + w, x);
-    }
-}
-
-// Zero n 32-bit words (a kernel rather than a memset, so that a captured
-// graph holds no memset node).
-__global__ void __launch_bounds__(256) k_zero_words(uint32_t* __restrict__ p, uint64_t n) {
-    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) p[i] = 0;
-}
-
 // The top T levels of every key's tree in one workgroup per key (blockIdx.x),
 // breadth-first: at level a each of the first count(a) threads expands one
 // node (eq. 3) into an LDS buffer, a barrier, the next level.  count(a) =
@@ -584,7 +491,7 @@ static int launch_threads(uint64_t count, uint32_t n_keys) { return count * n_ke
 
 hipError_t launch_dpf_eval(int device, const uint8_t* d_keys, uint32_t n, uint32_t n_keys, uint64_t n_leaves,
                            uint32_t* d_sel, uint64_t stride_words, void* scratch, uint64_t scratch_nodes,
-                           hipStream_t s, const DpfScanOut* scan) {
+                           hipStream_t s) {
     hipError_t e = setup_device(device);
     if (e != hipSuccess) return e;
     uint32_t steps[64][2];
@@ -613,30 +520,6 @@ hipError_t launch_dpf_eval(int device, const uint8_t* d_keys, uint32_t n, uint32
         const bool bits = k + 1 == ns;
         u32x4* out = bits ? nullptr : buf[slot];
         slot ^= 1;
-        if (bits && scan) {
-            const uint64_t words = (uint64_t)kDpfScanSlots * n_keys * (scan->rpad / 4);
-            hipLaunchKernelGGL(k_zero_words, dim3((uint32_t)std::min<uint64_t>((words + 255) / 256, 1024)), dim3(256),
-                               0, s, scan->acc, words);
-            const u32x4* db = reinterpret_cast<const u32x4*>(scan->db);
-            if (launch_threads(count, n_keys) == 1024) {
-                const uint32_t bytes = kTabBytes + 16 * scan->rpad;
-                const uint32_t ranges = (uint32_t)((count + 1023) / 1024);
-                if ((e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_dpf_scan<1024>), (int)bytes)))
-                    return e;
-                hipLaunchKernelGGL((k_dpf_scan<1024>), dim3((ranges * n_keys + 7) / 8 * 8), dim3(1024), bytes, s,
-                                   d_keys, kb, n, a, E, count, in, scratch_nodes, db, scan->cpb, scan->R, scan->rpad,
-                                   n_keys, ranges, scan->acc);
-            } else {
-                const uint32_t bytes = kTabBytes + 4 * scan->rpad;
-                const uint32_t ranges = (uint32_t)((count + 255) / 256);
-                if ((e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_dpf_scan<256>), (int)bytes))) return e;
-                hipLaunchKernelGGL((k_dpf_scan<256>), dim3((ranges * n_keys + 7) / 8 * 8), dim3(256), bytes, s,
-                                   d_keys, kb, n, a, E, count, in, scratch_nodes, db, scan->cpb, scan->R, scan->rpad,
-                                   n_keys, ranges, scan->acc);
-            }
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-            continue;
-        }
         if (launch_threads(count, n_keys) == 1024)
             launch_step<1024>(bits, dim3((uint32_t)((count + 1023) / 1024), n_keys), s, d_keys, kb, n, a, E, count, in,
                               scratch_nodes, out, scratch_nodes, d_sel, stride_words);

@@ -181,52 +181,4 @@ int pir_dpf_dpxor_async(pir_db* d, const void* d_keys, uint32_t n_keys, void* d_
     return PIR_OK;
 }
 
-int pir_dpf_dpxor_fused_async(pir_db* d, const void* d_keys, uint32_t n_keys, void* d_out, void* hip_stream) {
-    clear_error();
-    Db* db = reinterpret_cast<Db*>(d);
-    if (!db || !d_keys || !d_out) return fail(PIR_E_INVAL, "pir_dpf_dpxor_fused_async: NULL argument");
-    if (n_keys == 0 || n_keys > PIR_MAX_BATCH)
-        return fail(PIR_E_INVAL, "n_keys=%u outside [1, %u]", n_keys, PIR_MAX_BATCH);
-    if ((uintptr_t)d_keys % 16 != 0) return fail(PIR_E_INVAL, "d_keys must be 16-byte aligned");
-    const Geometry& g = db->geo;
-    if (g.R > kDpfScanMaxR) return fail(PIR_E_INVAL, "record_bytes %u > %u for the fused path", g.R, kDpfScanMaxR);
-    const uint32_t n = pir_dpf_domain_bits(g.n);
-    if (n > kMaxDomainBits) return fail(PIR_E_INVAL, "database domain 2^%u too large", n);
-    Ctx* ctx = db->ctx;
-    int rc = ctx->bind();
-    if (rc) return rc;
-    hipStream_t s = (hipStream_t)hip_stream;
-    const uint32_t gk = keys_per_group(n, g.n, n_keys);
-    const uint64_t nodes = dpf_scratch_nodes(n, g.n);
-    DevBuf *nb, *ab;
-    {
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        nb = &ctx->dpf_ws[s].nodes;
-        ab = &ctx->dpf_ws[s].sel;
-    }
-    if ((rc = grow(*nb, (size_t)gk * 2 * nodes * 16 + 16, s, "DPF scratch"))) return rc;
-    if ((rc = grow(*ab, (size_t)kDpfScanSlots * gk * g.rpad, s, "DPF answer slots"))) return rc;
-    const bool timed = ctx->timing_on.load();
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (timed) {
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        e0 = ctx->take_event();
-        e1 = ctx->take_event();
-    }
-    if (e0) (void)hipEventRecord(e0, s);
-    const uint64_t kb = dpf_key_bytes(n);
-    for (uint32_t k0 = 0; k0 < n_keys; k0 += gk) {
-        const uint32_t nk = n_keys - k0 < gk ? n_keys - k0 : gk;
-        const DpfScanOut scan{db->data.ptr, g.cpb, g.R, g.rpad, (uint32_t*)ab->ptr};
-        hipError_t e = launch_dpf_eval(ctx->device, (const uint8_t*)d_keys + (uint64_t)k0 * kb, n, nk, g.n, nullptr,
-                                       0, nb->ptr, nodes, s, &scan);
-        if (e != hipSuccess) return hip_fail(e, "fused DPF scan launch");
-        e = launch_stage2(g, kDpfScanSlots, nk, (const uint8_t*)ab->ptr, (uint8_t*)d_out + (uint64_t)k0 * g.R, s);
-        if (e != hipSuccess) return hip_fail(e, "fused DPF scan reduction");
-    }
-    if (e1) (void)hipEventRecord(e1, s);
-    if (timed && e0 && e1) ctx->add_timed(e0, e1, 3);
-    return PIR_OK;
-}
-
 }  // extern "C"

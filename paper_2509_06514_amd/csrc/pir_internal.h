@@ -105,20 +105,9 @@ int dpf_plan(uint32_t n, uint64_t n_leaves, uint32_t n_keys, uint32_t a0, uint32
 // full-domain evaluation of n_keys keys (device, dpf_key_bytes(n) apart):
 // selection words [0, ceil(n_leaves / 32)) of row q at d_sel + q * stride_words;
 // scratch holds 2 * n_keys * scratch_nodes 16-byte nodes
-// Where the last launch of an evaluation scans instead of writing bits: the
-// bit-sliced database (16-byte chunks, cpb per block) and the partial
-// answers, kDpfScanSlots x n_keys rows of rpad bytes (as 32-bit words) that
-// the launch zeroes and then XORs into; R <= kDpfScanMaxR.
-constexpr uint32_t kDpfScanSlots = 64;
-constexpr uint32_t kDpfScanMaxR = 4096;  // 64 KiB of table + 16 waves x rpad bytes within 160 KiB of LDS
-struct DpfScanOut {
-    const void* db;
-    uint32_t cpb, R, rpad;
-    uint32_t* acc;
-};
 hipError_t launch_dpf_eval(int device, const uint8_t* d_keys, uint32_t n, uint32_t n_keys, uint64_t n_leaves,
                            uint32_t* d_sel, uint64_t stride_words, void* scratch, uint64_t scratch_nodes,
-                           hipStream_t s, const DpfScanOut* scan = nullptr);
+                           hipStream_t s);
 void dpf_gen_host(uint64_t alpha, uint32_t n, const uint8_t root0[16], const uint8_t root1[16], uint8_t* key0,
                   uint8_t* key1);
 void aes128_encrypt_host(const uint8_t key[16], const uint8_t in[16], uint8_t out[16]);

@@ -207,148 +207,6 @@ struct MfmaAcc<false> {
     typedef i32x4 type;
 };
 
-template <int MT, bool F4>
-__global__ void __launch_bounds__(kThreads)
-k_stage1_mfma(const uint32_t* __restrict__ db, const uint32_t* __restrict__ sel,
-              uint8_t* __restrict__ partials, Stage1Params p) {
-    typedef typename MfmaAcc<F4>::type acc_t;
-    uint32_t group, ct, qt;
-    if (!decode_block(p.groups, p.n_ct, p.n_qt, group, ct, qt)) return;
-
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t j = lane & 15, g = lane >> 4;
-    const uint32_t q0 = qt * (16 * MT);
-    const uint64_t block_words = 8ull * p.R;
-
-    // this lane's 4 bit columns (one 16-byte chunk) within every block
-    const u32x4* dl = reinterpret_cast<const u32x4*>(db + ct * 256 + wave * 64 + 4 * j);
-    const uint64_t block_chunks = block_words / 4;
-
-    // this lane's query row in each row tile (A operand row i = j)
-    const uint32_t* srow[MT];
-    bool qok[MT];
-#pragma unroll
-    for (int rt = 0; rt < MT; ++rt) {
-        const uint32_t q = q0 + 16 * rt + j;
-        qok[rt] = q < p.q_total;
-        srow[rt] = sel + (uint64_t)(qok[rt] ? q : 0) * p.stride_words;
-    }
-
-    acc_t acc[MT][4];
-#pragma unroll
-    for (int rt = 0; rt < MT; ++rt)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) acc[rt][t] = acc_t{0, 0, 0, 0};
-
-    const uint64_t b_begin = (uint64_t)group * p.units_per_group;
-    const uint64_t b_end = (b_begin + p.units_per_group < p.n_units) ? b_begin + p.units_per_group : p.n_units;
-
-    // One K-step's raw words: B chunk per sub-step, A word per (row tile, sub-step).
-    struct Step {
-        u32x4 bw[4];
-        uint32_t aw[MT][4];
-    };
-    auto load_full = [&](uint64_t kb, Step& st) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const uint64_t blk = kb + 4 * g + s;
-            st.bw[s] = dl[blk * block_chunks];
-#pragma unroll
-            for (int rt = 0; rt < MT; ++rt) st.aw[rt][s] = srow[rt][blk];
-        }
-    };
-    auto load_tail = [&](uint64_t kb, Step& st) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const uint64_t blk = kb + 4 * g + s;
-            const bool ok = blk < b_end;
-            st.bw[s] = ok ? dl[blk * block_chunks] : u32x4{0, 0, 0, 0};
-#pragma unroll
-            for (int rt = 0; rt < MT; ++rt) st.aw[rt][s] = ok ? srow[rt][blk] : 0u;
-        }
-    };
-    auto compute = [&](const Step& st) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            if (F4) {
-                i32x8 bx[4];
-#pragma unroll
-                for (int t = 0; t < 4; ++t) bx[t] = spread_fp4_b(st.bw[s][t]);
-#pragma unroll
-                for (int rt = 0; rt < MT; ++rt) {
-                    const i32x8 ax = spread_fp4_a(st.aw[rt][s]);
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
-                        acc[rt][t] = (acc_t)__builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-                            ax, bx[t], (f32x4)acc[rt][t], 4, 4, 0, 127, 0, 127);
-                }
-            } else {
-                i32x4 blo[4], bhi[4];
-#pragma unroll
-                for (int t = 0; t < 4; ++t) spread_i8_stored(st.bw[s][t], blo[t], bhi[t]);
-#pragma unroll
-                for (int rt = 0; rt < MT; ++rt) {
-                    i32x4 alo, ahi;
-                    spread_i8(st.aw[rt][s], alo, ahi);
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        acc[rt][t] = (acc_t)__builtin_amdgcn_mfma_i32_16x16x64_i8(alo, blo[t], (i32x4)acc[rt][t], 0, 0, 0);
-                        acc[rt][t] = (acc_t)__builtin_amdgcn_mfma_i32_16x16x64_i8(ahi, bhi[t], (i32x4)acc[rt][t], 0, 0, 0);
-                    }
-                }
-            }
-        }
-    };
-
-    // Full K-steps, software-pipelined: the next step's loads are in flight
-    // while the current step runs on the matrix cores.  Then the ragged tail.
-    uint64_t kb = b_begin;
-    const uint64_t full_end = b_begin + (b_end - b_begin) / kMfmaBlocksPerStep * kMfmaBlocksPerStep;
-    if (kb < full_end) {
-        Step cur, nxt;
-        load_full(kb, cur);
-        for (; kb + kMfmaBlocksPerStep < full_end; kb += kMfmaBlocksPerStep) {
-            load_full(kb + kMfmaBlocksPerStep, nxt);
-            // keep the loads issued here, ahead of the matrix work (the
-            // scheduler would otherwise sink them past it)
-            asm volatile("" ::: "memory");
-            __builtin_amdgcn_sched_barrier(0);
-            compute(cur);
-            cur = nxt;
-        }
-        compute(cur);
-        kb = full_end;
-    }
-    if (kb < b_end) {
-        Step st;
-        load_tail(kb, st);
-        compute(st);
-    }
-
-    // Output layout of a 16x16 MFMA tile: lane holds column j = lane % 16 and
-    // rows 4*(lane/16) + r, r = 0..3.  Row = query q0 + 16*rt + 4g + r; column
-    // tile t of lane j = bit column 64*wave + 4j + t = bit (4j + t) % 8 of
-    // byte 8*wave + j/2 of the tile.  Lanes j and j^1 fill one byte together.
-#pragma unroll
-    for (int rt = 0; rt < MT; ++rt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            uint32_t nib = 0;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const uint32_t cnt = F4 ? (uint32_t)(float)acc[rt][t][r] : (uint32_t)acc[rt][t][r];
-                nib |= (cnt & 1u) << t;
-            }
-            const uint32_t other = (uint32_t)__shfl_xor((int)nib, 1);
-            const uint32_t q = q0 + 16 * rt + 4 * g + r;
-            if ((j & 1) == 0 && q < p.q_total) {
-                const uint32_t byte_pos = ct * 32 + wave * 8 + j / 2;
-                partials[((uint64_t)group * p.q_total + q) * p.rpad + byte_pos] = (uint8_t)(nib | (other << 4));
-            }
-        }
-}
-
 // Operand reads of one K-step from an LDS stage: four database chunks at
 // `b` + 0/1/2/3 KiB and MT selection quads at `a` + rt KiB.  The reads and
 // their lgkmcnt wait sit in one asm block, so the values are complete when
@@ -395,56 +253,6 @@ __device__ __forceinline__ void lds_read_step(uint32_t b, uint32_t a, u32x4 (&bw
     }
 }
 
-// Shared-spread helpers (each asm block waits for its own LDS traffic).
-// Four database chunks at b + 0/1/2/3 KiB and one selection quad at a.
-__device__ __forceinline__ void lds_read_b4a1(uint32_t b, uint32_t a, u32x4 (&bw)[4], u32x4& aw) {
-    asm volatile(
-        "ds_read_b128 %0, %5\n\t"
-        "ds_read_b128 %1, %5 offset:1024\n\t"
-        "ds_read_b128 %2, %5 offset:2048\n\t"
-        "ds_read_b128 %3, %5 offset:3072\n\t"
-        "ds_read_b128 %4, %6\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        : "=&v"(bw[0]), "=&v"(bw[1]), "=&v"(bw[2]), "=&v"(bw[3]), "=&v"(aw)
-        : "v"(b), "v"(a));
-}
-// Four 16-byte values to w + 0/1/2/3 KiB.
-__device__ __forceinline__ void lds_write_4(uint32_t w, const u32x4 (&v)[4]) {
-    asm volatile(
-        "ds_write_b128 %0, %1\n\t"
-        "ds_write_b128 %0, %2 offset:1024\n\t"
-        "ds_write_b128 %0, %3 offset:2048\n\t"
-        "ds_write_b128 %0, %4 offset:3072\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        :
-        : "v"(w), "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]));
-}
-// Sixteen 16-byte values from r + i KiB, i = 0..15.
-__device__ __forceinline__ void lds_read_16(uint32_t r, u32x4 (&v)[16]) {
-    asm volatile(
-        "ds_read_b128 %0, %16\n\t"
-        "ds_read_b128 %1, %16 offset:1024\n\t"
-        "ds_read_b128 %2, %16 offset:2048\n\t"
-        "ds_read_b128 %3, %16 offset:3072\n\t"
-        "ds_read_b128 %4, %16 offset:4096\n\t"
-        "ds_read_b128 %5, %16 offset:5120\n\t"
-        "ds_read_b128 %6, %16 offset:6144\n\t"
-        "ds_read_b128 %7, %16 offset:7168\n\t"
-        "ds_read_b128 %8, %16 offset:8192\n\t"
-        "ds_read_b128 %9, %16 offset:9216\n\t"
-        "ds_read_b128 %10, %16 offset:10240\n\t"
-        "ds_read_b128 %11, %16 offset:11264\n\t"
-        "ds_read_b128 %12, %16 offset:12288\n\t"
-        "ds_read_b128 %13, %16 offset:13312\n\t"
-        "ds_read_b128 %14, %16 offset:14336\n\t"
-        "ds_read_b128 %15, %16 offset:15360\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2]), "=&v"(v[3]), "=&v"(v[4]), "=&v"(v[5]), "=&v"(v[6]),
-          "=&v"(v[7]), "=&v"(v[8]), "=&v"(v[9]), "=&v"(v[10]), "=&v"(v[11]), "=&v"(v[12]), "=&v"(v[13]),
-          "=&v"(v[14]), "=&v"(v[15])
-        : "v"(r));
-}
-
 // Matrix-core scan with a multi-stage LDS ring.  Direct-to-LDS loads
 // (global_load_lds_dwordx4 / _dword) stream the next S-1 K-steps of database
 // chunks and selection words into LDS while the current K-step runs on the
@@ -461,13 +269,7 @@ __host__ __device__ constexpr uint32_t ring_bytes(int stages) {
     return (uint32_t)stages * (kStageDbBytes + 16u * MT * 16u * 4u);
 }
 
-//
-// With SA ("shared A"), the selection operand is spread once per workgroup
-// instead of once per wave: wave w spreads row tile w (its 16 queries) for
-// the step's four sub-steps and publishes the spread values through a
-// 16 KiB LDS buffer [row tile][sub-step][lane][16 B]; a second barrier per
-// step separates those writes from the reads.  (fp4, 64-query tiles.)
-template <int MT, bool F4, int S, bool SA>
+template <int MT, bool F4, int S>
 __global__ void __launch_bounds__(kThreads)
 k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ sel,
                   uint8_t* __restrict__ partials, Stage1Params p) {
@@ -476,11 +278,9 @@ k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
     constexpr int kLoadsPerStep = 4 + MT;  // per wave: 4 database chunks + MT selection rows-of-4
     constexpr uint32_t kStageSelBytes = QT * 16 * 4;
     static_assert(S >= 2 && S <= 8, "ring stages");
-    static_assert(!SA || (MT == 4 && F4), "shared spread: fp4, four row tiles");
     extern __shared__ __attribute__((aligned(16))) uint8_t pir_ring[];
     uint8_t* const ring_db = pir_ring;                        // S x [16 blocks][256 words]
     uint8_t* const ring_sel = pir_ring + S * kStageDbBytes;  // S x [QT rows][16 words]
-    uint8_t* const spread_a = ring_sel + S * kStageSelBytes;  // SA: [4 row tiles][4 sub-steps][64][16 B]
 
     uint32_t group, ct, qt;
     if (!decode_block(p.groups, p.n_ct, p.n_qt, group, ct, qt)) return;
@@ -561,45 +361,11 @@ k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
     // this lane's operand addresses inside stage 0; stage k adds k * stage size
     const uint32_t rd_db = (uint32_t)(uintptr_t)(ring_db + (4 * g) * 1024 + (64 * wave + 4 * j) * 4);
     const uint32_t rd_sel = (uint32_t)(uintptr_t)(ring_sel + j * 64 + (4 * g) * 4);
-    // SA: this wave's own selection quad (row 16*wave + j, words 4g..4g+3)
-    const uint32_t rd_own = (uint32_t)(uintptr_t)(ring_sel + (16 * wave + j) * 64 + (4 * g) * 4);
-    const uint32_t wr_spread = (uint32_t)(uintptr_t)(spread_a + (4 * wave) * 1024 + lane * 16);
-    const uint32_t rd_spread = (uint32_t)(uintptr_t)(spread_a + lane * 16);
     auto compute_slot = [&](uint32_t slot) {
         u32x4 bw[4];
-        if constexpr (SA) {
-            u32x4 own;
-            lds_read_b4a1(rd_db + slot * kStageDbBytes, rd_own + slot * kStageSelBytes, bw, own);
-            u32x4 sp[4];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const i32x8 x = spread_fp4_a(own[s]);
-                sp[s] = u32x4{(uint32_t)x[0], (uint32_t)x[1], (uint32_t)x[2], (uint32_t)x[3]};
-            }
-            lds_write_4(wr_spread, sp);
-            wg_barrier();  // every row tile's spread values are in LDS
-            u32x4 av[16];  // [row tile][sub-step]
-            lds_read_16(rd_spread, av);
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                i32x8 bx[4];
-#pragma unroll
-                for (int t = 0; t < 4; ++t) bx[t] = spread_fp4_b(bw[s][t]);
-#pragma unroll
-                for (int rt = 0; rt < MT; ++rt) {
-                    const u32x4 a4 = av[rt * 4 + s];
-                    const i32x8 ax = i32x8{(int32_t)a4[0], (int32_t)a4[1], (int32_t)a4[2], (int32_t)a4[3], 0, 0, 0, 0};
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
-                        acc[rt][t] = (acc_t)__builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-                            ax, bx[t], (f32x4)acc[rt][t], 4, 4, 0, 127, 0, 127);
-                }
-            }
-        } else {
-            u32x4 aw4[MT];
-            lds_read_step<MT>(rd_db + slot * kStageDbBytes, rd_sel + slot * kStageSelBytes, bw, aw4);
-            mma(bw, aw4);
-        }
+        u32x4 aw4[MT];
+        lds_read_step<MT>(rd_db + slot * kStageDbBytes, rd_sel + slot * kStageSelBytes, bw, aw4);
+        mma(bw, aw4);
     };
 
     const uint64_t b_begin = (uint64_t)group * p.units_per_group;
@@ -627,8 +393,7 @@ k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
     // last S-1 steps: everything is already in flight
     wait_vmcnt<0>();
     wg_barrier();
-    for (uint64_t k0 = k; k < nsteps; ++k) {
-        if (SA && k != k0) wg_barrier();  // the shared spread buffer has been read
+    for (; k < nsteps; ++k) {
         compute_slot(slot);
         slot = slot + 1 == S ? 0 : slot + 1;
     }
@@ -1279,27 +1044,22 @@ hipError_t launch_unslice(const Geometry& g, const uint32_t* src_block0, uint64_
 bool mfma_supported(uint32_t variant, const Geometry& g, uint32_t qt, uint32_t unroll) {
     if (variant != PIR_VARIANT_MFMA_F4 && variant != PIR_VARIANT_MFMA_I8) return false;
     if (g.R % 32 != 0) return false;  // whole 256-column tiles
-    // unroll selects the pipeline: 1 = one K-step ahead in registers;
-    // 2, 3, 4, 6 = an LDS ring of that many stages (that many minus one K-steps
-    // in flight), within the 160 KiB of LDS a workgroup may use; 7 = a
-    // 3-stage ring whose selection operand is spread once per workgroup
-    // (fp4, 64-query tiles)
-    if (unroll == 7) return variant == PIR_VARIANT_MFMA_F4 && qt == 64;
-    // 12, 13, 14 = split-K kernel on a ring of 2, 3, 4 stages (fp4, 64-query tiles)
-    if (unroll >= 12 && unroll <= 14) return variant == PIR_VARIANT_MFMA_F4 && qt == 64;
-    // 15 = split-K kernel, 2-stage ring, selection words in 4-step stages (fp4, 64-query tiles)
-    if (unroll == 15) return variant == PIR_VARIANT_MFMA_F4 && qt == 64;
-    if (unroll != 1 && unroll != 2 && unroll != 3 && unroll != 4 && unroll != 6) return false;
+    // unroll selects the pipeline: 2, 3, 4 = an LDS ring of that many stages
+    // (that many minus one K-steps in flight); 12 = the split-K kernel on a
+    // 2-stage ring (fp4, 64-query tiles); 15 = the split-K kernel whose
+    // selection words arrive four K-steps at a time (fp4, 64-query tiles)
+    if (unroll == 12 || unroll == 15) return variant == PIR_VARIANT_MFMA_F4 && qt == 64;
+    if (unroll != 2 && unroll != 3 && unroll != 4) return false;
     return qt == 16 || qt == 32 || qt == 64;
 }
 
-template <int MT, bool F4, int S, bool SA = false>
+template <int MT, bool F4, int S>
 static hipError_t launch_ring(dim3 grid, hipStream_t s, const uint32_t* db, const uint32_t* sel, uint8_t* partials,
                               const Stage1Params& p) {
-    constexpr uint32_t bytes = ring_bytes<MT>(S) + (SA ? 16u * 1024u : 0u);
-    const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_lds<MT, F4, S, SA>), (int)bytes);
+    constexpr uint32_t bytes = ring_bytes<MT>(S);
+    const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_lds<MT, F4, S>), (int)bytes);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_stage1_mfma_lds<MT, F4, S, SA>), grid, dim3(kThreads), bytes, s, db, sel, partials, p);
+    hipLaunchKernelGGL((k_stage1_mfma_lds<MT, F4, S>), grid, dim3(kThreads), bytes, s, db, sel, partials, p);
     return hipGetLastError();
 }
 
@@ -1356,35 +1116,23 @@ static hipError_t launch_mfma_t(const Geometry& g, const Plan& pl, const void* d
         case 2: return launch_ring<MT, F4, 2>(grid, s, d, sel, partials, p);
         case 3: return launch_ring<MT, F4, 3>(grid, s, d, sel, partials, p);
         case 4: return launch_ring<MT, F4, 4>(grid, s, d, sel, partials, p);
-        case 6: return launch_ring<MT, F4, 6>(grid, s, d, sel, partials, p);
-        case 7:
-            if constexpr (MT == 4 && F4) return launch_ring<4, true, 3, true>(grid, s, d, sel, partials, p);
-            return hipErrorInvalidValue;
         case 12:
-        case 13:
-        case 14:
-            if constexpr (MT == 4 && F4) {
-                if (pl.unroll == 12) return launch_ks<2>(grid, s, d, sel, partials, p);
-                if (pl.unroll == 13) return launch_ks<3>(grid, s, d, sel, partials, p);
-                return launch_ks<4>(grid, s, d, sel, partials, p);
-            }
+            if constexpr (MT == 4 && F4) return launch_ks<2>(grid, s, d, sel, partials, p);
             return hipErrorInvalidValue;
         case 15:
             if constexpr (MT == 4 && F4) return launch_ksw(grid, s, d, sel, partials, p);
             return hipErrorInvalidValue;
         default:
-            hipLaunchKernelGGL((k_stage1_mfma<MT, F4>), grid, dim3(kThreads), 0, s, d, sel, partials, p);
-            return hipGetLastError();
+            return hipErrorInvalidValue;
     }
 }
 
 template <int MT, bool F4>
 static hipError_t prepare_rings() {
     hipError_t e = hipSuccess;
-    if ((e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_lds<MT, F4, 2, false>), (int)ring_bytes<MT>(2))) ||
-        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_lds<MT, F4, 3, false>), (int)ring_bytes<MT>(3))) ||
-        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_lds<MT, F4, 4, false>), (int)ring_bytes<MT>(4))) ||
-        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_lds<MT, F4, 6, false>), (int)ring_bytes<MT>(6))))
+    if ((e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_lds<MT, F4, 2>), (int)ring_bytes<MT>(2))) ||
+        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_lds<MT, F4, 3>), (int)ring_bytes<MT>(3))) ||
+        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_lds<MT, F4, 4>), (int)ring_bytes<MT>(4))))
         return e;
     return hipSuccess;
 }
@@ -1394,11 +1142,7 @@ hipError_t prepare_scan_kernels() {
     if ((e = prepare_rings<1, true>()) || (e = prepare_rings<2, true>()) || (e = prepare_rings<4, true>()) ||
         (e = prepare_rings<1, false>()) || (e = prepare_rings<2, false>()) || (e = prepare_rings<4, false>()))
         return e;
-    if ((e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_lds<4, true, 3, true>),
-                                (int)(ring_bytes<4>(3) + 16u * 1024u))) ||
-        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ks<2>), (int)ring_bytes<4>(2))) ||
-        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ks<3>), (int)ring_bytes<4>(3))) ||
-        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ks<4>), (int)ring_bytes<4>(4))) ||
+    if ((e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ks<2>), (int)ring_bytes<4>(2))) ||
         (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksw), (int)kWsLdsBytes)))
         return e;
     return hipSuccess;

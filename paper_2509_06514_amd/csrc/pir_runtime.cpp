@@ -882,12 +882,17 @@ int pir_tune(pir_db* d, uint32_t q, pir_kernel_cfg* out) {
     }
     // matrix-core tiles are at least 16 queries: from 8 queries up, one
     // 16-query tile with idle rows is still worth timing
+    // (the split-K kernel on a 2-stage ring, unroll 12, is left out: the form
+    // with wide selection reads, 15, beats it everywhere and takes its place;
+    // 12 remains that form's fallback for rows off 16-byte boundaries)
     for (uint32_t v : {PIR_VARIANT_MFMA_I8, PIR_VARIANT_MFMA_F4})
         for (uint32_t qt : {16u, 32u, 64u})
-            for (uint32_t u : {1u, 2u, 3u, 4u, 6u, 7u, 12u, 13u, 14u, 15u})
+            for (uint32_t u : {2u, 3u, 4u, 15u})
                 if (q >= 8 && qt <= std::max<uint32_t>(qmax_tile, 16) && mfma_supported(v, g, qt, u))
                     cands.push_back({v, qt, u, 0});
-    // grid variants of each: the default record-group count, half and double
+    // grid variants of each: the default record-group count, half and
+    // double, and four times for many query tiles (their workgroups share
+    // each record tile through L2, so more, shorter groups balance better)
     std::vector<pir_kernel_cfg> all;
     for (auto c : cands) {
         Plan p;
@@ -895,7 +900,8 @@ int pir_tune(pir_db* d, uint32_t q, pir_kernel_cfg* out) {
         p.qt = c.q_tile;
         p.unroll = c.unroll;
         if (finish_plan(g, q, p)) continue;
-        for (uint32_t mult : {1u, 2u, 4u}) {
+        for (uint32_t mult : {1u, 2u, 4u, 8u}) {
+            if (mult == 8 && p.n_qt < 4) continue;
             pir_kernel_cfg cc = c;
             cc.groups = std::max<uint32_t>(1, p.groups * mult / 2);
             all.push_back(cc);

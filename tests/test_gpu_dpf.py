@@ -138,12 +138,10 @@ def _load(ctx, n, r, seed):
     return dbh, ctx.load_db(dbh)
 
 
-@pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("N,R", [(3000, 32), (1 << 12, 8), (777, 256), (1, 32), (70001, 13), (5000, 1000),
                                  (33, 3)])
-def test_dpf_dpxor_two_server(ctx, N, R, fused):
-    # ans(k0) XOR ans(k1) = D[alpha]; ans(k0) = oracle scan of oracle-evaluated bits;
-    # fused: the last tree level and the scan in one kernel
+def test_dpf_dpxor_two_server(ctx, N, R):
+    # ans(k0) XOR ans(k1) = D[alpha]; ans(k0) = oracle scan of oracle-evaluated bits
     dbh, db = _load(ctx, N, R, synth.S_DB + 50 + R)
     n = pir.dpf_domain_bits(N)
     rng = np.random.default_rng(N)
@@ -157,7 +155,7 @@ def test_dpf_dpxor_two_server(ctx, N, R, fused):
     d_keys = torch.from_numpy(keys).to("cuda:0")
     d_out = torch.empty((len(keys), R), dtype=torch.uint8, device="cuda:0")
     d_out.fill_(0xEE)
-    db.dpf_dpxor_async(d_keys, len(keys), d_out, fused=fused)
+    db.dpf_dpxor_async(d_keys, len(keys), d_out)
     torch.cuda.synchronize()
     ans = d_out.cpu().numpy()
     m = len(alphas)
@@ -169,10 +167,9 @@ def test_dpf_dpxor_two_server(ctx, N, R, fused):
     db.free()
 
 
-def test_dpf_dpxor_fused_matches_pipeline_large(ctx):
+def test_dpf_dpxor_large_in_key_groups(ctx):
     # 2^22 records x 32 B, 8 keys (4 pairs), in two calls with different key
-    # counts: the fused and the pipelined answers are identical and each pair
-    # reconstructs its record
+    # counts: the same rows, and each pair reconstructs its record
     N, R = 1 << 22, 32
     dbh, db = _load(ctx, N, R, synth.S_DB + 57)
     n = pir.dpf_domain_bits(N)
@@ -180,30 +177,15 @@ def test_dpf_dpxor_fused_matches_pipeline_large(ctx):
     ks = [pir.dpf_gen(a, n, *_roots(synth.S_KEY + 700 + i)) for i, a in enumerate(alphas)]
     keys = np.stack([k[0] for k in ks] + [k[1] for k in ks])
     d_keys = torch.from_numpy(keys).to("cuda:0")
-    for nk in (8, 3):
-        a = torch.full((nk, R), 0xEE, dtype=torch.uint8, device="cuda:0")
-        b = torch.full((nk, R), 0x11, dtype=torch.uint8, device="cuda:0")
-        db.dpf_dpxor_async(d_keys, nk, a, fused=True)
-        db.dpf_dpxor_async(d_keys, nk, b, fused=False)
-        torch.cuda.synchronize()
-        assert np.array_equal(a.cpu().numpy(), b.cpu().numpy()), nk
-    full = torch.empty((8, R), dtype=torch.uint8, device="cuda:0")
-    db.dpf_dpxor_async(d_keys, 8, full, fused=True)
+    full = torch.full((8, R), 0xEE, dtype=torch.uint8, device="cuda:0")
+    part = torch.full((3, R), 0x11, dtype=torch.uint8, device="cuda:0")
+    db.dpf_dpxor_async(d_keys, 8, full)
+    db.dpf_dpxor_async(d_keys, 3, part)
     torch.cuda.synchronize()
     ans = full.cpu().numpy()
+    assert np.array_equal(part.cpu().numpy(), ans[:3])
     for i, al in enumerate(alphas):
         assert np.array_equal(ans[i] ^ ans[4 + i], dbh[al]), al
-    db.free()
-
-
-def test_dpf_dpxor_fused_rejects_wide_records(ctx):
-    dbh, db = _load(ctx, 100, 4097, synth.S_DB + 58)
-    keys = torch.zeros((1, pir.dpf_key_bytes(pir.dpf_domain_bits(100))), dtype=torch.uint8, device="cuda:0")
-    out = torch.empty((1, 4097), dtype=torch.uint8, device="cuda:0")
-    with pytest.raises(pir.PirError):
-        db.dpf_dpxor_async(keys, 1, out, fused=True)
-    db.dpf_dpxor_async(keys, 1, out)  # the pipelined path takes any record size
-    torch.cuda.synchronize()
     db.free()
 
 

@@ -85,11 +85,10 @@ def test_n28r32_variants_match_oracle(db_n28r32, q):
     dbh, db, sel, d_sel, stride, orc = db_n28r32
     want = orc.first(q)
     for cfg in (pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 4, 0),
-                pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 7, 0),
                 pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 12, 0),
                 pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 15, 0),
-                pir.KernelCfg(pir.PIR_VARIANT_MFMA_I8, 64, 6, 0),
-                pir.KernelCfg(pir.PIR_VARIANT_MFMA_I8, 32, 1, 0),
+                pir.KernelCfg(pir.PIR_VARIANT_MFMA_I8, 64, 4, 0),
+                pir.KernelCfg(pir.PIR_VARIANT_MFMA_I8, 32, 2, 0),
                 pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 32, 3, 0),
                 pir.KernelCfg(pir.PIR_VARIANT_VALU, 16, 4, 0)):
         _assert_rows(_run(db, d_sel, stride, q, cfg), want, f"q={q} {cfg}")

@@ -195,9 +195,9 @@ MFMA_VARIANTS = [pir.PIR_VARIANT_MFMA_F4, pir.PIR_VARIANT_MFMA_I8]
 def _mfma_cfg_exists(variant, qt, unroll):
     """The matrix-core (q_tile, unroll) combinations the library compiles."""
     f4 = variant == pir.PIR_VARIANT_MFMA_F4
-    if unroll in (1, 2, 3, 4, 6):
+    if unroll in (2, 3, 4):
         return qt in (16, 32, 64)
-    if unroll in (7, 12, 13, 14, 15):
+    if unroll in (12, 15):
         return f4 and qt == 64
     return False
 
@@ -215,9 +215,9 @@ def test_mfma_variants(ctx, variant, n, r):
     for q in qs:
         d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
         for qt in (16, 32, 64):
-            # registers, LDS rings of 2/3/4/6 stages, shared spread, split K on 2/3/4
-            # stages, split K with selection words 4 K-steps at a time
-            for unroll in (1, 2, 3, 4, 6, 7, 12, 13, 14, 15):
+            # LDS rings of 2/3/4 stages, split K on a 2-stage ring, split K with
+            # selection words 4 K-steps at a time
+            for unroll in (2, 3, 4, 12, 15):
                 if not _mfma_cfg_exists(variant, qt, unroll):
                     continue
                 for groups in (0, 3, 1):
@@ -245,9 +245,9 @@ def test_mfma_counts_exact_on_large_group(ctx, variant):
     d_sel = torch.from_numpy(host).to("cuda:0")
     d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
     want3 = oracle.dpxor(dbh, rnd[0])
-    cfgs = [(16, 1), (16, 3), (16, 6)]
+    cfgs = [(16, 2), (16, 3), (16, 4)]
     if variant == pir.PIR_VARIANT_MFMA_F4:
-        cfgs += [(64, 13), (64, 15)]  # split K: each half's counts and their sum stay exact
+        cfgs += [(64, 12), (64, 15)]  # split K: each half's counts and their sum stay exact
     for qt, unroll in cfgs:
         d_out.fill_(0)
         db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride, cfg=pir.KernelCfg(variant, qt, unroll, 1))
