@@ -94,6 +94,8 @@ def kernel_name(cfg, r):
         return "k_stage1_mfma_ks<2>"
     if cfg.unroll == 15:  # split K, 2-stage ring, selection words 4 K-steps at a time
         return "k_stage1_mfma_ksw"
+    if cfg.unroll == 16:  # the same with wave-private database stages
+        return "k_stage1_mfma_ksp"
     return None
 
 
@@ -308,7 +310,7 @@ def variant_sweep(ctx, db, d_sel, stride, n, r, q, d_out, torch, pir, reps=3):
         for v in (2, 3):
             for qt in (16, 32, 64):
                 if qt <= max(p2, 16):
-                    fams[v] += [(qt, u) for u in (2, 3, 4) + ((15,) if v == 3 and qt == 64 else ())]
+                    fams[v] += [(qt, u) for u in (2, 3, 4) + ((15, 16) if v == 3 and qt == 64 else ())]
     ref, same, out = None, True, {}
     for v, cands in fams.items():
         best = None

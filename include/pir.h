@@ -178,7 +178,8 @@ typedef struct pir_kernel_cfg {
     uint32_t unroll;  /* VALU: blocks per wave iteration; MFMA: 2/3/4 = LDS ring of that
                          many stages, 12 = split-K kernel on a 2-stage ring (fp4, q_tile 64),
                          15 = split-K kernel on a 2-stage ring whose selection words arrive
-                         4 K-steps at a time (fp4, q_tile 64); 0 = default */
+                         4 K-steps at a time, 16 = the same with wave-private database
+                         stages (both fp4, q_tile 64); 0 = default */
     uint32_t groups;  /* record groups = partial results per query (0 = default) */
 } pir_kernel_cfg;
 
@@ -454,7 +455,10 @@ int pir_fp_inner_async(pir_fpdb* db, const void* d_v, uint64_t v_stride, uint32_
                        void* hip_stream);
 
 /* Q queries, host in and out, synchronous: v holds q rows v_stride >= N
- * bytes apart, out receives q rows of L bytes. */
+ * bytes apart, out receives q rows of L bytes.  As for pir_dpxor_batch,
+ * pinned buffers (pir_host_alloc) are copied to and from the device
+ * directly; pageable rows go through two pinned staging pieces of at most
+ * 16 MiB each, whatever q is. */
 int pir_fp_inner(pir_fpdb* db, const uint8_t* v, uint64_t v_stride, uint32_t q, uint8_t* out);
 
 /* ---------------------------------------------------------------- measurement */

@@ -358,13 +358,20 @@ class FpDatabase:
     def handle(self):
         return self._h
 
-    def inner(self, v_rows):
-        """Q queries, host in/out: v_rows (Q, >= N) uint8 (< 128) -> (Q, L) answers."""
+    def inner(self, v_rows, out=None):
+        """Q queries, host in/out: v_rows (Q, >= N) uint8 (< 128) -> (Q, L) answers.
+
+        Arrays from pinned_empty (for v_rows and out) skip the library's staging copies.
+        """
         v_rows = _u8(v_rows)
         if v_rows.ndim == 1:
             v_rows = v_rows.reshape(1, -1)
         q, stride = v_rows.shape
-        out = np.empty((q, self.record_elems), np.uint8)
+        shape = (q, self.record_elems)
+        if out is None:
+            out = np.empty(shape, np.uint8)
+        elif out.dtype != np.uint8 or out.shape != shape or not out.flags.c_contiguous:
+            raise ValueError(f"out must be a C-contiguous uint8 array of shape {shape}")
         check(lib().pir_fp_inner(self._h, _ptr(v_rows), stride, q, _ptr(out)), "pir_fp_inner")
         return out
 

@@ -256,23 +256,16 @@ int pir_fp_inner(pir_fpdb* d, const uint8_t* v, uint64_t v_stride, uint32_t q, u
     const uint64_t dstride = fp_pitch(db->tiles * 64);
     const size_t v_bytes = (size_t)dstride * q, out_bytes = (size_t)q * db->L;
     hipError_t e;
-    if ((e = ex->h_sel.ensure(v_bytes)) != hipSuccess) return hip_fail(e, "pinned query staging");
     if ((e = ex->d_sel.ensure(v_bytes)) != hipSuccess) return hip_fail(e, "device query buffer");
-    if ((e = ex->h_out.ensure(out_bytes)) != hipSuccess) return hip_fail(e, "pinned answer staging");
     if ((e = ex->d_out.ensure(out_bytes)) != hipSuccess) return hip_fail(e, "device answer buffer");
-    uint8_t* hs = (uint8_t*)ex->h_sel.ptr;
-    pack_rows(hs, v, q, v_stride, db->n, dstride);
-    if ((e = hipMemcpyAsync(ex->d_sel.ptr, hs, v_bytes, hipMemcpyHostToDevice, ex->stream)) != hipSuccess)
-        return hip_fail(e, "query upload");
+    // a pinned caller's rows are copied as they are, so the device rows' tails
+    // past N keep older bytes: they meet the zero padding records of the last
+    // tile only and add nothing
+    if ((rc = upload_rows(ex, v, v_stride, db->n, q, (uint8_t*)ex->d_sel.ptr, dstride, "query upload"))) return rc;
     if ((rc = enqueue_fp(*db, (const uint8_t*)ex->d_sel.ptr, dstride, q, (uint8_t*)ex->d_out.ptr, ex->partials,
                          ex->stream, true)))
         return rc;
-    if ((e = hipMemcpyAsync(ex->h_out.ptr, ex->d_out.ptr, out_bytes, hipMemcpyDeviceToHost, ex->stream)) !=
-        hipSuccess)
-        return hip_fail(e, "answer download");
-    if ((e = hipStreamSynchronize(ex->stream)) != hipSuccess) return hip_fail(e, "F_p inner product");
-    memcpy(out, ex->h_out.ptr, out_bytes);
-    return PIR_OK;
+    return download_answers(ex, ex->d_out.ptr, out, out_bytes, "F_p inner product");
 }
 
 }  // extern "C"

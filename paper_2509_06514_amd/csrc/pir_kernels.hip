@@ -338,8 +338,7 @@ k_stage1_mfma_lds(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
                     const i32x8 ax = spread_fp4_a(aw4[rt][s]);
 #pragma unroll
                     for (int t = 0; t < 4; ++t)
-                        acc[rt][t] = (acc_t)__builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-                            ax, bx[t], (f32x4)acc[rt][t], 4, 4, 0, 127, 0, 127);
+                        acc[rt][t] = (acc_t)mfma_fp4(ax, bx[t], (f32x4)acc[rt][t]);
                 }
             } else {
                 i32x4 blo[4], bhi[4];
@@ -546,8 +545,7 @@ k_stage1_mfma_ks(const uint32_t* __restrict__ db, const uint32_t* __restrict__ s
                 const i32x8 ax = spread_fp4_a(aw[rt][sl]);
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
-                    acc[rt][t] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(ax, bx[t], acc[rt][t], 4, 4, 0,
-                                                                                 127, 0, 127);
+                    acc[rt][t] = mfma_fp4(ax, bx[t], acc[rt][t]);
             }
         }
     };
@@ -681,16 +679,115 @@ __device__ __forceinline__ void lds_read_ksw(uint32_t b, uint32_t a, u32x4 (&bw)
 }
 static_assert(4 * kWsRowGroup == 4352, "row-tile offset in lds_read_ksw");
 
-// The contraction, the database loads and the K-half fold are those of
-// k_stage1_mfma_ks<2>.  Selection stage 0 is loaded before the first step
-// and stage m + 1 during the steps of stage m, one 1 KiB load per wave and
-// step (load 4s + w in step s by wave w); the steps of the last stage load
-// no selection words.  Each step waits for all of its wave's earlier loads
-// and then meets the others at a barrier, as in the 2-stage ring.
+// ---- the contraction of one K-step of the split-K kernels, in issue order
+//
+// A wave's K-step is 64 products (2 sub-steps x 4 row tiles x 8 column
+// tiles).  Each operand word is spread into E2M1 values by four "pieces"
+// (spread_fp4_a/b: three masks and one shift-and-mask).  An in-order wave can
+// issue vector-ALU work while the matrix core runs its previous product, but
+// not ahead of a product it is waiting to issue, so the pieces are laid out
+// between the products: the first sub-step's selection operands and its
+// first database operand come first; then, column tile by column tile, each
+// product is followed by one or two pieces of the operands the later
+// products need (the next column tile of this sub-step, then the second
+// sub-step's operands).  Scheduling barriers keep the compiler to this order.
+
+// Spread operands of one K-step: a[sl][rt] (selection, row tile rt) and
+// b[sl][t] (database, column tile t) for sub-step sl, E2M1 in four dwords.
+struct KswOps {
+    i32x4 a[2][4];
+    i32x4 b[2][8];
+};
+
+__device__ __forceinline__ i32x8 widen(const i32x4& x) { return i32x8{x[0], x[1], x[2], x[3], 0, 0, 0, 0}; }
+
+// piece P of spread_fp4_a / spread_fp4_b
+template <int P>
+__device__ __forceinline__ int32_t piece_a(uint32_t w) {
+    if constexpr (P == 0) return (int32_t)(w & 0x11111111u);
+    else if constexpr (P == 1) return (int32_t)(w & 0x22222222u);
+    else if constexpr (P == 2) return (int32_t)(w & 0x44444444u);
+    else return (int32_t)((w >> 1) & 0x44444444u);
+}
+template <int P>
+__device__ __forceinline__ int32_t piece_b(uint32_t w) {
+    if constexpr (P == 0) return (int32_t)(w & 0x44444444u);
+    else if constexpr (P == 1) return (int32_t)(w & 0x22222222u);
+    else if constexpr (P == 2) return (int32_t)(w & 0x11111111u);
+    else return (int32_t)((w >> 3) & 0x11111111u);
+}
+
+// piece I (0..19) of sub-step SL's first operands: the selection operand of
+// row tile I / 4 (I < 16), else the database operand of column tile 0
+template <int SL, int I>
+__device__ __forceinline__ void pro_piece(KswOps& o, const u32x4 (&bw)[4], const u32x2 (&aw)[4]) {
+    if constexpr (I < 16) o.a[SL][I / 4][I % 4] = piece_a<I % 4>(aw[I / 4][SL]);
+    else o.b[SL][0][I % 4] = piece_b<I % 4>(bw[2 * SL][0]);
+}
+// piece P of the database operand of sub-step SL, column tile T
+template <int SL, int T, int P>
+__device__ __forceinline__ void b_piece(KswOps& o, const u32x4 (&bw)[4]) {
+    o.b[SL][T][P] = piece_b<P>(bw[2 * SL + (T >> 2)][T & 3]);
+}
+template <int SL, int I>
+__device__ __forceinline__ void pro_all(KswOps& o, const u32x4 (&bw)[4], const u32x2 (&aw)[4]) {
+    if constexpr (I < 20) {
+        pro_piece<SL, I>(o, bw, aw);
+        pro_all<SL, I + 1>(o, bw, aw);
+    }
+}
+// piece K (0..5) issued among the first sub-step's products of column tile
+// T: the next database operand (K < 4, T < 7), else the second sub-step's
+// first operands
+template <int T, int K>
+__device__ __forceinline__ void group_piece(KswOps& o, const u32x4 (&bw)[4], const u32x2 (&aw)[4]) {
+    if constexpr (T < 7 && K < 4) b_piece<0, T + 1, K>(o, bw);
+    else if constexpr (T < 7) pro_piece<1, 2 * T + (K - 4)>(o, bw, aw);
+    else pro_piece<1, 14 + K>(o, bw, aw);
+}
+
+// product M (sub-step M / 32, column tile M % 32 / 4, row tile M % 4), then
+// its pieces: 2, 1, 2, 1 per column tile in the first sub-step, one (the next
+// database operand's) in the second
+template <int M>
+__device__ __forceinline__ void ksw_sched(f32x4 (&acc)[4][8], KswOps& o, const u32x4 (&bw)[4], const u32x2 (&aw)[4]) {
+    if constexpr (M < 64) {
+        constexpr int sl = M / 32, t = (M % 32) / 4, rt = M % 4;
+        acc[rt][t] = mfma_fp4(widen(o.a[sl][rt]), widen(o.b[sl][t]), acc[rt][t]);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (sl == 0) {
+            constexpr int k0 = rt == 0 ? 0 : rt == 1 ? 2 : rt == 2 ? 3 : 5;
+            group_piece<t, k0>(o, bw, aw);
+            if constexpr (rt == 0 || rt == 2) group_piece<t, k0 + 1>(o, bw, aw);
+        } else if constexpr (t < 7) {
+            b_piece<1, t + 1, rt>(o, bw);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        ksw_sched<M + 1>(acc, o, bw, aw);
+    }
+}
+
+// acc[rt][t] += the K-step whose words are bw (database: bw[2*sl + half] for
+// sub-step sl, columns 64*half + 4j ..) and aw (selection: aw[rt][sl])
+__device__ __forceinline__ void ksw_step_sched(f32x4 (&acc)[4][8], const u32x4 (&bw)[4], const u32x2 (&aw)[4]) {
+    KswOps o;
+    pro_all<0, 0>(o, bw, aw);
+    __builtin_amdgcn_sched_barrier(0);
+    ksw_sched<0>(acc, o, bw, aw);
+}
+
+// The database loads and the K-half fold are those of k_stage1_mfma_ks<2>;
+// the contraction is ksw_step_sched.  Selection stage 0 is loaded before the
+// first step and stage m + 1 during the steps of stage m, one 1 KiB load per
+// wave and step (load 4s + w in step s by wave w); the steps of the last
+// stage load no selection words.  Each step waits for all of its wave's
+// earlier loads and then meets the others at a barrier, as in the 2-stage
+// ring.
 __global__ void __launch_bounds__(kThreads)
 k_stage1_mfma_ksw(const uint32_t* __restrict__ db, const uint32_t* __restrict__ sel,
                   uint8_t* __restrict__ partials, Stage1Params p) {
     constexpr int MT = 4, NT = 8, QT = 64;
+    constexpr uint32_t RG = kWsRowGroup, kSelStage = kWsStageSelBytes;
     extern __shared__ __attribute__((aligned(16))) uint8_t pir_ring[];
     uint8_t* const ring_db = pir_ring;
     uint8_t* const ring_sel = pir_ring + 2 * kStageDbBytes;
@@ -748,7 +845,7 @@ k_stage1_mfma_ksw(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
         if (4 * m + 3 >= nsteps && 4 * m + (ch >> 2) >= nsteps) off -= 16 * (ch & ~3u);
         __builtin_amdgcn_global_load_lds(
             reinterpret_cast<const uint32_t*>(uniform_ptr(sel_row[st] + (uint64_t)m * 256) + off),
-            ring_sel + (m & 1) * kWsStageSelBytes + (4 * st + wave) * kWsRowGroup, 16, 0, 0);
+            ring_sel + (m & 1) * kSelStage + (4 * st + wave) * RG, 16, 0, 0);
     };
 
     f32x4 acc[MT][NT];
@@ -759,26 +856,11 @@ k_stage1_mfma_ksw(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
 
     // bw[2*sl + half]: sub-step 2h + sl, columns 128c + 64*half + 4j .. +3;
     // aw[rt][sl]: selection word of row 16rt + j for that sub-step
-    auto mma = [&](const u32x4 bw[4], const u32x2 aw[MT]) {
-#pragma unroll
-        for (int sl = 0; sl < 2; ++sl) {
-            i32x8 bx[NT];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) bx[t] = spread_fp4_b(bw[2 * sl + (t >> 2)][t & 3]);
-#pragma unroll
-            for (int rt = 0; rt < MT; ++rt) {
-                const i32x8 ax = spread_fp4_a(aw[rt][sl]);
-#pragma unroll
-                for (int t = 0; t < NT; ++t)
-                    acc[rt][t] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(ax, bx[t], acc[rt][t], 4, 4, 0,
-                                                                                 127, 0, 127);
-            }
-        }
-    };
+    auto mma = [&](const u32x4 (&bw)[4], const u32x2 (&aw)[MT]) { ksw_step_sched(acc, bw, aw); };
     const uint32_t rd_db =
         (uint32_t)(uintptr_t)(ring_db + (4 * g + 2 * h) * 1024 + (128 * c + 4 * j) * 4);
     // row 16rt + j, word 16s + 4g + 2h (chunk 4s + g) of stage buffer m & 1
-    const uint32_t rd_sel = (uint32_t)(uintptr_t)(ring_sel + (j >> 2) * kWsRowGroup + (j & 3) * 256 +
+    const uint32_t rd_sel = (uint32_t)(uintptr_t)(ring_sel + (j >> 2) * RG + (j & 3) * 256 +
                                                   16 * (g ^ (j & 3)) + 8 * h);
 
     if (nsteps > 0) {
@@ -797,11 +879,207 @@ k_stage1_mfma_ksw(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
             if (4 * (m + 1) < nsteps) issue_sel(m + 1, st);
             u32x4 bw[4];
             u32x2 aw[MT];
-            lds_read_ksw(rd_db + (k & 1) * kStageDbBytes, rd_sel + (m & 1) * kWsStageSelBytes + 64 * st, bw, aw);
+            lds_read_ksw(rd_db + (k & 1) * kStageDbBytes, rd_sel + (m & 1) * kSelStage + 64 * st, bw, aw);
             mma(bw, aw);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
+    wait_vmcnt<0>();
+
+    // ragged tail (fewer than 16 blocks) straight from memory
+    const uint64_t kb = b_begin + (uint64_t)nsteps * kMfmaBlocksPerStep;
+    if (kb < b_end) {
+        const u32x4* dl = reinterpret_cast<const u32x4*>(db + ct * 256 + 128 * c + 4 * j);
+        u32x4 bw[4];
+        u32x2 aw[MT];
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+            const uint64_t blk = kb + 4 * g + 2 * h + sl;
+            const bool ok = blk < b_end;
+            bw[2 * sl] = ok ? dl[blk * (block_words / 4)] : u32x4{0, 0, 0, 0};
+            bw[2 * sl + 1] = ok ? dl[blk * (block_words / 4) + 16] : u32x4{0, 0, 0, 0};
+#pragma unroll
+            for (int rt = 0; rt < MT; ++rt) {
+                const uint32_t q = q0 + 16 * rt + j;
+                aw[rt][sl] = (ok && q < p.q_total) ? sel[(uint64_t)q * p.stride_words + blk] : 0u;
+            }
+        }
+        mma(bw, aw);
+    }
+
+    // answer bits: lane holds columns 128c + 64*half + 4j + t' of rows
+    // 16rt + 4g + r; bit 8r + 4*half + t' of par[rt]
+    uint32_t par[MT];
+#pragma unroll
+    for (int rt = 0; rt < MT; ++rt) {
+        par[rt] = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) par[rt] |= (((uint32_t)acc[rt][t][r]) & 1u) << (8 * r + t);
+    }
+    // fold the K halves through LDS (every load has landed and, after this
+    // barrier, every wave has read its last stage)
+    __syncthreads();
+    u32x4* fold = reinterpret_cast<u32x4*>(pir_ring) + c * 64 + lane;
+    if (h == 1) *fold = u32x4{par[0], par[1], par[2], par[3]};
+    __syncthreads();  // the fold writes are complete and visible
+    if (h == 1) return;
+    const u32x4 o = *fold;
+    par[0] ^= o[0];
+    par[1] ^= o[1];
+    par[2] ^= o[2];
+    par[3] ^= o[3];
+#pragma unroll
+    for (int rt = 0; rt < MT; ++rt) {
+        const uint32_t other = (uint32_t)__shfl_xor((int)par[rt], 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t q = q0 + 16 * rt + 4 * g + r;
+            const uint32_t mine = par[rt] >> (8 * r), theirs = other >> (8 * r);
+            if ((j & 1) == 0 && q < p.q_total) {
+                uint8_t* dst = partials + ((uint64_t)group * p.q_total + q) * p.rpad + ct * 32 + 16 * c + j / 2;
+                dst[0] = (uint8_t)((mine & 0xF) | ((theirs & 0xF) << 4));
+                dst[8] = (uint8_t)(((mine >> 4) & 0xF) | (theirs & 0xF0));
+            }
+        }
+    }
+}
+
+// Split-K kernel with wave-private database stages: each wave's quarter of a
+// K-step's database words (its K half: blocks 4g + 2h + sl; its 128 columns)
+// is read by that wave alone, so each wave streams it into its own two-slot
+// LDS ring, one K-step ahead, and waits only for its own loads: no barrier
+// per K-step.  The selection words, shared by the two waves of a K
+// half, move in the stages of k_stage1_mfma_ksw (4 K-steps, double-buffered),
+// issued at the first step of the stage before; the waves meet at a barrier
+// once per stage.  Loads past the group's end re-read valid data that is
+// never used.
+constexpr uint32_t kSpLdsBytes = 2 * kWsStageSelBytes + 4 * 2 * 4096;
+
+__global__ void __launch_bounds__(kThreads)
+k_stage1_mfma_ksp(const uint32_t* __restrict__ db, const uint32_t* __restrict__ sel,
+                  uint8_t* __restrict__ partials, Stage1Params p) {
+    constexpr int MT = 4, NT = 8, QT = 64;
+    constexpr uint32_t RG = kWsRowGroup, kSelStage = kWsStageSelBytes;
+    extern __shared__ __attribute__((aligned(16))) uint8_t pir_ring[];
+    uint8_t* const ring_sel = pir_ring;
+
+    uint32_t group, ct, qt;
+    if (!decode_block(p.groups, p.n_ct, p.n_qt, group, ct, qt)) return;
+
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t c = wave & 1, h = wave >> 1;
+    const uint32_t j = lane & 15, g = lane >> 4;
+    const uint32_t q0 = qt * QT;
+    const uint64_t block_words = 8ull * p.R;
+    const uint64_t b_begin = (uint64_t)group * p.units_per_group;
+    const uint64_t b_end = (b_begin + p.units_per_group < p.n_units) ? b_begin + p.units_per_group : p.n_units;
+    const uint32_t nsteps = (uint32_t)((b_end - b_begin) / kMfmaBlocksPerStep);
+
+    // this wave's ring: slot s at ring_db + s * 4096; load i of a step puts
+    // block 4i + 2h + sl (sl = lane / 32), words 128c + 4(lane % 32) .. +3,
+    // at i * 1024 + 16 * lane
+    uint8_t* const ring_db = pir_ring + 2 * kSelStage + wave * (2 * 4096);
+    const uint8_t* db_wave = reinterpret_cast<const uint8_t*>(db + ct * 256 + (b_begin + 2 * h) * block_words + 128 * c);
+    const uint32_t db_lane = (uint32_t)((lane >> 5) * block_words * 4 + 16 * (lane & 31));
+    auto issue_db = [&](uint32_t k, uint32_t slot) {
+        const uint32_t ks = k < nsteps ? k : nsteps - 1;
+        uint8_t* dst = ring_db + slot * 4096;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint8_t* base =
+                uniform_ptr(db_wave + ((uint64_t)ks * kMfmaBlocksPerStep + 4 * i) * block_words * 4);
+            // database chunks are read once: nontemporal (cache policy NT = 2)
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint32_t*>(base + db_lane), dst + i * 1024, 16,
+                                             0, 2);
+        }
+    };
+
+    // selection loads as in k_stage1_mfma_ksw: load 4s + w of a stage covers
+    // rows q0 + 4(4s + w) .. +3; stage m goes to buffer m & 1, read from
+    // stage min(m, last stage)
+    const uint32_t ch = (lane & 15) ^ (lane >> 4);
+    const uint8_t* sel_row[4];
+    uint32_t sel_off[4];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+        uint32_t r0 = q0 + 4 * (4 * st + wave);
+        const bool any = r0 < p.q_total;
+        if (!any) r0 = q0;
+        const uint32_t rl = (any && r0 + lane / 16 < p.q_total) ? lane / 16 : 0;
+        sel_row[st] = reinterpret_cast<const uint8_t*>(sel + (uint64_t)r0 * p.stride_words + b_begin);
+        sel_off[st] = rl * (uint32_t)(p.stride_words * 4) + 16 * ch;
+    }
+    const uint32_t last_stage = nsteps > 0 ? (nsteps - 1) / 4 : 0;
+    auto issue_sel = [&](uint32_t m) {
+        const uint32_t ms = m < last_stage ? m : last_stage;
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            uint32_t off = sel_off[st];
+            if (4 * ms + 3 >= nsteps && 4 * ms + (ch >> 2) >= nsteps) off -= 16 * (ch & ~3u);
+            __builtin_amdgcn_global_load_lds(
+                reinterpret_cast<const uint32_t*>(uniform_ptr(sel_row[st] + (uint64_t)ms * 256) + off),
+                ring_sel + (m & 1) * kSelStage + (4 * st + wave) * RG, 16, 0, 0);
+        }
+    };
+
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int rt = 0; rt < MT; ++rt)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[rt][t] = f32x4{0, 0, 0, 0};
+
+    auto mma = [&](const u32x4 (&bw)[4], const u32x2 (&aw)[MT]) { ksw_step_sched(acc, bw, aw); };
+    // bw[2*sl + half] (block 4g + 2h + sl, words 128c + 64*half + 4j) at
+    // g * 1024 + sl * 512 + half * 256 + 16j of a slot
+    const uint32_t rd_db = (uint32_t)(uintptr_t)(ring_db + g * 1024 + 16 * j);
+    // row 16rt + j, word 16s + 4g + 2h (chunk 4s + g) of stage buffer m & 1
+    const uint32_t rd_sel = (uint32_t)(uintptr_t)(ring_sel + (j >> 2) * RG + (j & 3) * 256 +
+                                                  16 * (g ^ (j & 3)) + 8 * h);
+    auto read_ops = [&](uint32_t b, uint32_t a, u32x4 (&bw)[4], u32x2 (&aw)[MT]) {
+        asm volatile(
+            "ds_read_b128 %0, %8\n\t"
+            "ds_read_b128 %1, %8 offset:256\n\t"
+            "ds_read_b128 %2, %8 offset:512\n\t"
+            "ds_read_b128 %3, %8 offset:768\n\t"
+            "ds_read_b64 %4, %9\n\t"
+            "ds_read_b64 %5, %9 offset:4352\n\t"
+            "ds_read_b64 %6, %9 offset:8704\n\t"
+            "ds_read_b64 %7, %9 offset:13056\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(bw[0]), "=&v"(bw[1]), "=&v"(bw[2]), "=&v"(bw[3]), "=&v"(aw[0]), "=&v"(aw[1]),
+              "=&v"(aw[2]), "=&v"(aw[3])
+            : "v"(b), "v"(a));
+    };
+
+    if (nsteps > 0) {
+        issue_sel(0);
+        issue_db(0, 0);
+    }
+    for (uint32_t m = 0; 4 * m < nsteps; ++m) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            const uint32_t k = 4 * m + st;
+            if (k >= nsteps) break;
+            // this wave's database loads of step k were its last: all of its
+            // loads have landed (the selection loads of stage m with them)
+            wait_vmcnt<0>();
+            if (st == 0) {
+                // ... for every wave; stage m - 1's buffer has been read
+                wg_barrier();
+                issue_sel(m + 1);
+            }
+            issue_db(k + 1, (k + 1) & 1);
+            u32x4 bw[4];
+            u32x2 aw[MT];
+            read_ops(rd_db + (k & 1) * 4096, rd_sel + (m & 1) * kSelStage + 64 * st, bw, aw);
+            mma(bw, aw);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    wait_vmcnt<0>();
 
     // ragged tail (fewer than 16 blocks) straight from memory
     const uint64_t kb = b_begin + (uint64_t)nsteps * kMfmaBlocksPerStep;
@@ -1047,8 +1325,9 @@ bool mfma_supported(uint32_t variant, const Geometry& g, uint32_t qt, uint32_t u
     // unroll selects the pipeline: 2, 3, 4 = an LDS ring of that many stages
     // (that many minus one K-steps in flight); 12 = the split-K kernel on a
     // 2-stage ring (fp4, 64-query tiles); 15 = the split-K kernel whose
-    // selection words arrive four K-steps at a time (fp4, 64-query tiles)
-    if (unroll == 12 || unroll == 15) return variant == PIR_VARIANT_MFMA_F4 && qt == 64;
+    // selection words arrive four K-steps at a time, 16 = the same with
+    // wave-private database stages (both fp4, 64-query tiles)
+    if (unroll == 12 || unroll == 15 || unroll == 16) return variant == PIR_VARIANT_MFMA_F4 && qt == 64;
     if (unroll != 2 && unroll != 3 && unroll != 4) return false;
     return qt == 16 || qt == 32 || qt == 64;
 }
@@ -1078,16 +1357,29 @@ static hipError_t launch_ks(dim3 grid, hipStream_t s, const uint32_t* db, const 
     return hipGetLastError();
 }
 
+// The split-K kernels with wide selection loads move 16 bytes per lane: rows
+// must start on 16-byte boundaries; other pitches take the 4-byte loads of
+// the split-K ring kernel
+static bool wide_sel_ok(const uint32_t* sel, const Stage1Params& p) {
+    return p.stride_words <= kWsMaxStrideWords && p.stride_words % 4 == 0 &&
+           (reinterpret_cast<uintptr_t>(sel) & 15) == 0;
+}
+
 static hipError_t launch_ksw(dim3 grid, hipStream_t s, const uint32_t* db, const uint32_t* sel, uint8_t* partials,
                              const Stage1Params& p) {
-    // the wide selection loads move 16 bytes per lane: rows must start on
-    // 16-byte boundaries; other pitches take the 4-byte loads of the split-K
-    // ring kernel
-    const bool aligned16 = p.stride_words % 4 == 0 && (reinterpret_cast<uintptr_t>(sel) & 15) == 0;
-    if (p.stride_words > kWsMaxStrideWords || !aligned16) return launch_ks<2>(grid, s, db, sel, partials, p);
+    if (!wide_sel_ok(sel, p)) return launch_ks<2>(grid, s, db, sel, partials, p);
     const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksw), (int)kWsLdsBytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_stage1_mfma_ksw, grid, dim3(kThreads), kWsLdsBytes, s, db, sel, partials, p);
+    return hipGetLastError();
+}
+
+static hipError_t launch_ksp(dim3 grid, hipStream_t s, const uint32_t* db, const uint32_t* sel, uint8_t* partials,
+                             const Stage1Params& p) {
+    if (!wide_sel_ok(sel, p)) return launch_ks<2>(grid, s, db, sel, partials, p);
+    const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksp), (int)kSpLdsBytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_stage1_mfma_ksp, grid, dim3(kThreads), kSpLdsBytes, s, db, sel, partials, p);
     return hipGetLastError();
 }
 
@@ -1122,6 +1414,9 @@ static hipError_t launch_mfma_t(const Geometry& g, const Plan& pl, const void* d
         case 15:
             if constexpr (MT == 4 && F4) return launch_ksw(grid, s, d, sel, partials, p);
             return hipErrorInvalidValue;
+        case 16:
+            if constexpr (MT == 4 && F4) return launch_ksp(grid, s, d, sel, partials, p);
+            return hipErrorInvalidValue;
         default:
             return hipErrorInvalidValue;
     }
@@ -1143,7 +1438,8 @@ hipError_t prepare_scan_kernels() {
         (e = prepare_rings<1, false>()) || (e = prepare_rings<2, false>()) || (e = prepare_rings<4, false>()))
         return e;
     if ((e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ks<2>), (int)ring_bytes<4>(2))) ||
-        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksw), (int)kWsLdsBytes)))
+        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksw), (int)kWsLdsBytes)) ||
+        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksp), (int)kSpLdsBytes)))
         return e;
     return hipSuccess;
 }

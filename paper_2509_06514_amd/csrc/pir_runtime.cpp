@@ -481,6 +481,66 @@ void pack_rows(uint8_t* dst, const uint8_t* src, uint32_t nr, uint64_t src_strid
     pack_range(dst, src, src_stride, row_bytes, dstride, 0, (uint64_t)nr * dstride);
 }
 
+// Whether [p, p + bytes) is pinned host memory (pir_host_alloc / hipHostMalloc)
+// that the device can copy from or to directly.  A pageable pointer makes the
+// query fail; its error is cleared so later launch checks do not see it.
+static bool pinned_host(const void* p, size_t bytes) {
+    for (const void* x : {p, (const void*)((const uint8_t*)p + (bytes ? bytes - 1 : 0))}) {
+        hipPointerAttribute_t a;
+        if (hipPointerGetAttributes(&a, x) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        if (a.type != hipMemoryTypeHost) return false;
+    }
+    return true;
+}
+
+// Bytes per staging half for the pageable path.
+constexpr uint64_t kStageChunk = 16ull << 20;
+
+int upload_rows(Exec* ex, const uint8_t* src, uint64_t src_stride, uint64_t row_bytes, uint32_t q, uint8_t* dst,
+                uint64_t dstride, const char* what) {
+    hipError_t e;
+    if (pinned_host(src, (size_t)src_stride * (q - 1) + row_bytes)) {
+        if ((e = hipMemcpy2DAsync(dst, dstride, src, src_stride, row_bytes, q, hipMemcpyHostToDevice, ex->stream)) !=
+            hipSuccess)
+            return hip_fail(e, what);
+        return PIR_OK;
+    }
+    const uint64_t total = dstride * q;
+    const uint64_t chunk = std::min<uint64_t>(total, kStageChunk);
+    if ((e = ex->h_sel.ensure((size_t)(2 * chunk))) != hipSuccess) return hip_fail(e, "pinned staging");
+    for (uint64_t off = 0, c = 0; off < total; off += chunk, ++c) {
+        const uint64_t len = std::min<uint64_t>(chunk, total - off);
+        const int half = (int)(c & 1);
+        // the upload that last used this half has finished
+        if (c >= 2 && (e = hipEventSynchronize(ex->staged[half])) != hipSuccess) return hip_fail(e, what);
+        uint8_t* hs = (uint8_t*)ex->h_sel.ptr + half * chunk;
+        pack_range(hs, src, src_stride, row_bytes, dstride, off, len);
+        if ((e = hipMemcpyAsync(dst + off, hs, (size_t)len, hipMemcpyHostToDevice, ex->stream)) != hipSuccess)
+            return hip_fail(e, what);
+        if ((e = hipEventRecord(ex->staged[half], ex->stream)) != hipSuccess) return hip_fail(e, what);
+    }
+    return PIR_OK;
+}
+
+int download_answers(Exec* ex, const void* src, uint8_t* out, size_t bytes, const char* what) {
+    hipError_t e;
+    if (pinned_host(out, bytes)) {
+        if ((e = hipMemcpyAsync(out, src, bytes, hipMemcpyDeviceToHost, ex->stream)) != hipSuccess)
+            return hip_fail(e, "answer download");
+        if ((e = hipStreamSynchronize(ex->stream)) != hipSuccess) return hip_fail(e, what);
+        return PIR_OK;
+    }
+    if ((e = ex->h_out.ensure(bytes)) != hipSuccess) return hip_fail(e, "pinned answer staging");
+    if ((e = hipMemcpyAsync(ex->h_out.ptr, src, bytes, hipMemcpyDeviceToHost, ex->stream)) != hipSuccess)
+        return hip_fail(e, "answer download");
+    if ((e = hipStreamSynchronize(ex->stream)) != hipSuccess) return hip_fail(e, what);
+    memcpy(out, ex->h_out.ptr, bytes);
+    return PIR_OK;
+}
+
 int check_async_args(Db* db, const void* d_sel, uint64_t sel_stride, uint32_t q, void* d_out) {
     if (!db || !d_sel || !d_out) return fail(PIR_E_INVAL, "NULL argument");
     if (q == 0 || q > PIR_MAX_BATCH) return fail(PIR_E_INVAL, "q=%u outside [1, %u]", q, PIR_MAX_BATCH);
@@ -740,30 +800,9 @@ int pir_dpxor_batch_async(pir_db* d, const void* d_sel, uint64_t sel_stride, uin
     return pir_dpxor_batch_async_cfg(d, d_sel, sel_stride, q, d_out, hip_stream, nullptr);
 }
 
-// Whether [p, p + bytes) is pinned host memory (pir_host_alloc / hipHostMalloc)
-// that the device can copy from or to directly.  A pageable pointer makes the
-// query fail; its error is cleared so later launch checks do not see it.
-static bool pinned_host(const void* p, size_t bytes) {
-    for (const void* x : {p, (const void*)((const uint8_t*)p + (bytes ? bytes - 1 : 0))}) {
-        hipPointerAttribute_t a;
-        if (hipPointerGetAttributes(&a, x) != hipSuccess) {
-            (void)hipGetLastError();
-            return false;
-        }
-        if (a.type != hipMemoryTypeHost) return false;
-    }
-    return true;
-}
-
-// Bytes per staging half for the pageable path.
-constexpr uint64_t kStageChunk = 16ull << 20;
-
-// Synchronous path: upload, scan, download on a pooled stream.  Pinned
-// selection rows (and a pinned answer buffer) are copied straight to (from)
-// the device with a pitched copy; pageable rows are packed, in the device
-// layout, into two pinned staging halves of 16 MiB in turn (a chunk may end
-// inside a row), so that packing one chunk overlaps the upload of the one
-// before.
+// Synchronous path: upload, scan, download on a pooled stream (upload_rows,
+// download_answers: pinned buffers are copied directly, pageable ones through
+// bounded pinned staging).
 int pir_dpxor_batch(pir_db* d, const uint8_t* sel_bits, uint64_t sel_stride, uint32_t q, uint8_t* out) {
     clear_error();
     Db* db = reinterpret_cast<Db*>(d);
@@ -790,51 +829,17 @@ int pir_dpxor_batch(pir_db* d, const uint8_t* sel_bits, uint64_t sel_stride, uin
     } rel{ctx, ex};
     const uint64_t dstride = (4ull * g.nb + 255) / 256 * 256;  // device row pitch
     const size_t sel_bytes = (size_t)dstride * q, out_bytes = (size_t)g.R * q;
-    const bool sel_pinned = pinned_host(sel_bits, (size_t)sel_stride * (q - 1) + row_bytes);
-    const bool out_pinned = pinned_host(out, out_bytes);
     hipError_t e;
     if ((e = ex->d_sel.ensure(sel_bytes)) != hipSuccess) return hip_fail(e, "device selection buffer");
     if ((e = ex->d_out.ensure(out_bytes)) != hipSuccess) return hip_fail(e, "device answer buffer");
     if ((e = ex->partials.ensure(partial_bytes(g, p, q))) != hipSuccess) return hip_fail(e, "workspace");
     uint8_t* const ds = (uint8_t*)ex->d_sel.ptr;
-    if (sel_pinned) {
-        // row tails past ceil(N/8) bytes are never read by the scans
-        if ((e = hipMemcpy2DAsync(ds, dstride, sel_bits, sel_stride, row_bytes, q, hipMemcpyHostToDevice,
-                                  ex->stream)) != hipSuccess)
-            return hip_fail(e, "selection upload");
-    } else {
-        const uint64_t chunk = std::min<uint64_t>(sel_bytes, kStageChunk);
-        if ((e = ex->h_sel.ensure((size_t)(2 * chunk))) != hipSuccess) return hip_fail(e, "pinned selection staging");
-        for (uint64_t off = 0, c = 0; off < sel_bytes; off += chunk, ++c) {
-            const uint64_t len = std::min<uint64_t>(chunk, sel_bytes - off);
-            const int half = (int)(c & 1);
-            // the upload that last used this half has finished
-            if (c >= 2 && (e = hipEventSynchronize(ex->staged[half])) != hipSuccess)
-                return hip_fail(e, "selection staging");
-            uint8_t* hs = (uint8_t*)ex->h_sel.ptr + half * chunk;
-            pack_range(hs, sel_bits, sel_stride, row_bytes, dstride, off, len);
-            if ((e = hipMemcpyAsync(ds + off, hs, (size_t)len, hipMemcpyHostToDevice, ex->stream)) != hipSuccess)
-                return hip_fail(e, "selection upload");
-            if ((e = hipEventRecord(ex->staged[half], ex->stream)) != hipSuccess)
-                return hip_fail(e, "selection staging");
-        }
-    }
+    // row tails past ceil(N/8) bytes are never read by the scans
+    if ((rc = upload_rows(ex, sel_bits, sel_stride, row_bytes, q, ds, dstride, "selection upload"))) return rc;
     rc = ctx->launch_scan(*db, p, (const uint32_t*)ds, dstride / 4, q, (uint8_t*)ex->d_out.ptr,
                            (uint8_t*)ex->partials.ptr, ex->stream);
     if (rc) return rc;
-    if (out_pinned) {
-        if ((e = hipMemcpyAsync(out, ex->d_out.ptr, out_bytes, hipMemcpyDeviceToHost, ex->stream)) != hipSuccess)
-            return hip_fail(e, "answer download");
-        if ((e = hipStreamSynchronize(ex->stream)) != hipSuccess) return hip_fail(e, "scan");
-        return PIR_OK;
-    }
-    if ((e = ex->h_out.ensure(out_bytes)) != hipSuccess) return hip_fail(e, "pinned answer staging");
-    if ((e = hipMemcpyAsync(ex->h_out.ptr, ex->d_out.ptr, out_bytes, hipMemcpyDeviceToHost, ex->stream)) !=
-        hipSuccess)
-        return hip_fail(e, "answer download");
-    if ((e = hipStreamSynchronize(ex->stream)) != hipSuccess) return hip_fail(e, "scan");
-    memcpy(out, ex->h_out.ptr, out_bytes);
-    return PIR_OK;
+    return download_answers(ex, ex->d_out.ptr, out, out_bytes, "scan");
 }
 
 int pir_dpxor(pir_db* d, const uint8_t* sel_bits, uint8_t* out_record) {
@@ -882,12 +887,12 @@ int pir_tune(pir_db* d, uint32_t q, pir_kernel_cfg* out) {
     }
     // matrix-core tiles are at least 16 queries: from 8 queries up, one
     // 16-query tile with idle rows is still worth timing
-    // (the split-K kernel on a 2-stage ring, unroll 12, is left out: the form
-    // with wide selection reads, 15, beats it everywhere and takes its place;
-    // 12 remains that form's fallback for rows off 16-byte boundaries)
+    // (the split-K kernel on a 2-stage ring, unroll 12, is left out: the
+    // forms with wide selection reads, 15 and 16, beat it everywhere and take
+    // its place; 12 remains their fallback for rows off 16-byte boundaries)
     for (uint32_t v : {PIR_VARIANT_MFMA_I8, PIR_VARIANT_MFMA_F4})
         for (uint32_t qt : {16u, 32u, 64u})
-            for (uint32_t u : {2u, 3u, 4u, 15u})
+            for (uint32_t u : {2u, 3u, 4u, 15u, 16u})
                 if (q >= 8 && qt <= std::max<uint32_t>(qmax_tile, 16) && mfma_supported(v, g, qt, u))
                     cands.push_back({v, qt, u, 0});
     // grid variants of each: the default record-group count, half and

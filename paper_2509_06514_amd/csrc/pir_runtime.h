@@ -63,6 +63,18 @@ struct Exec {
     hipEvent_t staged[2] = {nullptr, nullptr};  // uploads out of the two staging halves
 };
 
+// Host rows -> device layout and device answers -> host, for the synchronous
+// calls, all on ex->stream.  upload_rows copies q rows of row_bytes bytes
+// (src_stride apart) to dst at a pitch of dstride: pinned rows with one
+// pitched copy (the device rows' tails past row_bytes are then left as they
+// were), pageable rows packed, tails zeroed, into two pinned staging halves
+// of at most 16 MiB in turn, so that packing one piece overlaps the upload
+// of the one before.  download_answers copies bytes from src to out and
+// waits for the stream: straight into a pinned out, else through ex->h_out.
+int upload_rows(Exec* ex, const uint8_t* src, uint64_t src_stride, uint64_t row_bytes, uint32_t q, uint8_t* dst,
+                uint64_t dstride, const char* what);
+int download_answers(Exec* ex, const void* src, uint8_t* out, size_t bytes, const char* what);
+
 struct TimedPair {
     hipEvent_t a, b;
     int stage;

@@ -106,6 +106,14 @@ __device__ __forceinline__ i32x8 spread_fp4_b(uint32_t w) {  // w in stored orde
     return r;
 }
 
+// One 16x16x128 product on E2M1 operands (the low four dwords of each i32x8;
+// the spreads above leave the high four zero).  Zero block-scale operands
+// make the compiler emit the unscaled instruction,
+// v_mfma_f32_16x16x128_f8f6f4 with four-register fp4 sources.
+__device__ __forceinline__ f32x4 mfma_fp4(const i32x8& a, const i32x8& b, const f32x4& c) {
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 4, 4, 0, 0, 0, 0);
+}
+
 constexpr uint32_t kStageDbBytes = 16 * 256 * 4;
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));

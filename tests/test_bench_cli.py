@@ -27,6 +27,7 @@ def test_more_than_one_gpu_exits_with_a_message():
     ((2, 16, 4, 0), 32, "k_stage1_mfma_lds<1, false, 4>"),
     ((3, 64, 12, 0), 32, "k_stage1_mfma_ks<2>"),
     ((3, 64, 15, 0), 32, "k_stage1_mfma_ksw"),
+    ((3, 64, 16, 0), 32, "k_stage1_mfma_ksp"),
 ])
 def test_kernel_names_follow_the_plan(cfg, r, name):
     assert bench.kernel_name(pir.KernelCfg(*cfg), r) == name

@@ -160,3 +160,35 @@ def test_recommended_pitch(ctx, n):
     assert np.array_equal(d_out.cpu().numpy(), want)
     assert np.array_equal(db.inner(rows[:, :n]), want)  # synchronous call, staged at the same pitch
     db.free()
+
+
+def test_sync_staging_pieces_and_pinned(ctx):
+    # The synchronous call with more query bytes than the two 16 MiB staging
+    # pieces (pageable rows: packed piece by piece, pieces reused), and with
+    # pinned rows and answers (one pitched copy each way).  The pinned call
+    # after a larger database's leaves older bytes in the device rows' tails
+    # past N: they meet only the zero padding records and change nothing.
+    L, p = 16, 101
+    n_big, n_small, q = (1 << 21) + 37, 4097, 24   # 24 rows x ~2 MiB: four pieces
+    D_big = _db(n_big, L, p, synth.S_DB + 400)
+    D_small = _db(n_small, L, p, synth.S_DB + 401)
+    big = ctx.load_fp_db(D_big, p)
+    small = ctx.load_fp_db(D_small, p)
+    rows = _queries(q, n_big + 3, synth.S_SEL + 400)
+    want_async = _async(big, rows[:, :n_big])
+    got = big.inner(rows)                            # pageable, 3 bytes of junk per row past N
+    assert np.array_equal(got, want_async)
+    for i in (0, 13, q - 1):
+        assert np.array_equal(got[i], oracle.fp_inner(D_big, rows[i, :n_big], p)), i
+    p_rows = pir.pinned_empty(rows.shape)
+    p_rows[:] = rows
+    p_out = pir.pinned_empty((q, L))
+    assert big.inner(p_rows, out=p_out) is p_out
+    assert np.array_equal(p_out, want_async)
+    p_small = pir.pinned_empty((q, n_small))
+    p_small[:] = rows[:, :n_small]
+    got_small = small.inner(p_small, out=pir.pinned_empty((q, L)))
+    for i in range(q):
+        assert np.array_equal(got_small[i], oracle.fp_inner(D_small, rows[i, :n_small], p)), i
+    small.free()
+    big.free()

@@ -197,7 +197,7 @@ def _mfma_cfg_exists(variant, qt, unroll):
     f4 = variant == pir.PIR_VARIANT_MFMA_F4
     if unroll in (2, 3, 4):
         return qt in (16, 32, 64)
-    if unroll in (12, 15):
+    if unroll in (12, 15, 16):
         return f4 and qt == 64
     return False
 
@@ -216,8 +216,9 @@ def test_mfma_variants(ctx, variant, n, r):
         d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
         for qt in (16, 32, 64):
             # LDS rings of 2/3/4 stages, split K on a 2-stage ring, split K with
-            # selection words 4 K-steps at a time
-            for unroll in (2, 3, 4, 12, 15):
+            # selection words 4 K-steps at a time (shared and wave-private
+            # database stages)
+            for unroll in (2, 3, 4, 12, 15, 16):
                 if not _mfma_cfg_exists(variant, qt, unroll):
                     continue
                 for groups in (0, 3, 1):
@@ -247,7 +248,7 @@ def test_mfma_counts_exact_on_large_group(ctx, variant):
     want3 = oracle.dpxor(dbh, rnd[0])
     cfgs = [(16, 2), (16, 3), (16, 4)]
     if variant == pir.PIR_VARIANT_MFMA_F4:
-        cfgs += [(64, 12), (64, 15)]  # split K: each half's counts and their sum stay exact
+        cfgs += [(64, 12), (64, 15), (64, 16)]  # split K: each half's counts and their sum stay exact
     for qt, unroll in cfgs:
         d_out.fill_(0)
         db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride, cfg=pir.KernelCfg(variant, qt, unroll, 1))
@@ -320,7 +321,7 @@ def test_wide_selection_kernel_unaligned_rows(ctx, n, r):
     q = 64
     sel = synth.selections(n, q, seed=0x16B + n, stride=stride)
     want = oracle.dpxor_batch(dbh, sel)
-    cfgs = [pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 15, 0)]
+    cfgs = [pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 15, 0), pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 16, 0)]
     d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
     for cfg in cfgs:
         for base in (0, 4):
@@ -332,13 +333,14 @@ def test_wide_selection_kernel_unaligned_rows(ctx, n, r):
                 db.dpxor_batch_async(d_sel, qq, d_out, sel_stride=stride, cfg=cfg)
                 torch.cuda.synchronize()
                 assert np.array_equal(d_out.cpu().numpy()[:qq], want[:qq]), (cfg, base, qq)
-    cfg = cfgs[0]
     # an aligned pitch (a multiple of 16 bytes) on the same rows
     stride16 = (stride + 15) // 16 * 16
     rows = np.zeros((q, stride16), np.uint8)
     rows[:, :stride] = sel
-    d_out.fill_(0xEE)
-    db.dpxor_batch_async(torch.from_numpy(rows).to("cuda:0"), q, d_out, sel_stride=stride16, cfg=cfg)
-    torch.cuda.synchronize()
-    assert np.array_equal(d_out.cpu().numpy(), want)
+    d_rows = torch.from_numpy(rows).to("cuda:0")
+    for cfg in cfgs:
+        d_out.fill_(0xEE)
+        db.dpxor_batch_async(d_rows, q, d_out, sel_stride=stride16, cfg=cfg)
+        torch.cuda.synchronize()
+        assert np.array_equal(d_out.cpu().numpy(), want), cfg
     db.free()
