@@ -953,8 +953,7 @@ k_stage1_mfma_ksw(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
 // per K-step.  The selection words, shared by the two waves of a K
 // half, move in the stages of k_stage1_mfma_ksw (4 K-steps, double-buffered),
 // issued at the first step of the stage before; the waves meet at a barrier
-// once per stage.  Loads past the group's end re-read valid data that is
-// never used.
+// once per stage.
 constexpr uint32_t kSpLdsBytes = 2 * kWsStageSelBytes + 4 * 2 * 4096;
 
 __global__ void __launch_bounds__(kThreads)
@@ -985,12 +984,11 @@ k_stage1_mfma_ksp(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
     const uint8_t* db_wave = reinterpret_cast<const uint8_t*>(db + ct * 256 + (b_begin + 2 * h) * block_words + 128 * c);
     const uint32_t db_lane = (uint32_t)((lane >> 5) * block_words * 4 + 16 * (lane & 31));
     auto issue_db = [&](uint32_t k, uint32_t slot) {
-        const uint32_t ks = k < nsteps ? k : nsteps - 1;
         uint8_t* dst = ring_db + slot * 4096;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const uint8_t* base =
-                uniform_ptr(db_wave + ((uint64_t)ks * kMfmaBlocksPerStep + 4 * i) * block_words * 4);
+                uniform_ptr(db_wave + ((uint64_t)k * kMfmaBlocksPerStep + 4 * i) * block_words * 4);
             // database chunks are read once: nontemporal (cache policy NT = 2)
             __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint32_t*>(base + db_lane), dst + i * 1024, 16,
                                              0, 2);
@@ -998,8 +996,7 @@ k_stage1_mfma_ksp(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
     };
 
     // selection loads as in k_stage1_mfma_ksw: load 4s + w of a stage covers
-    // rows q0 + 4(4s + w) .. +3; stage m goes to buffer m & 1, read from
-    // stage min(m, last stage)
+    // rows q0 + 4(4s + w) .. +3; stage m goes to buffer m & 1
     const uint32_t ch = (lane & 15) ^ (lane >> 4);
     const uint8_t* sel_row[4];
     uint32_t sel_off[4];
@@ -1012,15 +1009,15 @@ k_stage1_mfma_ksp(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
         sel_row[st] = reinterpret_cast<const uint8_t*>(sel + (uint64_t)r0 * p.stride_words + b_begin);
         sel_off[st] = rl * (uint32_t)(p.stride_words * 4) + 16 * ch;
     }
-    const uint32_t last_stage = nsteps > 0 ? (nsteps - 1) / 4 : 0;
+    // a chunk of a K-step past the group's last full step re-reads the same
+    // position of the stage's first step (valid, never used)
     auto issue_sel = [&](uint32_t m) {
-        const uint32_t ms = m < last_stage ? m : last_stage;
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
             uint32_t off = sel_off[st];
-            if (4 * ms + 3 >= nsteps && 4 * ms + (ch >> 2) >= nsteps) off -= 16 * (ch & ~3u);
+            if (4 * m + 3 >= nsteps && 4 * m + (ch >> 2) >= nsteps) off -= 16 * (ch & ~3u);
             __builtin_amdgcn_global_load_lds(
-                reinterpret_cast<const uint32_t*>(uniform_ptr(sel_row[st] + (uint64_t)ms * 256) + off),
+                reinterpret_cast<const uint32_t*>(uniform_ptr(sel_row[st] + (uint64_t)m * 256) + off),
                 ring_sel + (m & 1) * kSelStage + (4 * st + wave) * RG, 16, 0, 0);
         }
     };
@@ -1069,9 +1066,9 @@ k_stage1_mfma_ksp(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
             if (st == 0) {
                 // ... for every wave; stage m - 1's buffer has been read
                 wg_barrier();
-                issue_sel(m + 1);
+                if (4 * (m + 1) < nsteps) issue_sel(m + 1);
             }
-            issue_db(k + 1, (k + 1) & 1);
+            if (k + 1 < nsteps) issue_db(k + 1, (k + 1) & 1);
             u32x4 bw[4];
             u32x2 aw[MT];
             read_ops(rd_db + (k & 1) * 4096, rd_sel + (m & 1) * kSelStage + 64 * st, bw, aw);
