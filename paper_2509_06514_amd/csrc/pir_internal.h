@@ -83,6 +83,10 @@ hipError_t launch_stage1_mfma(const Geometry& g, const Plan& p, const void* db, 
 hipError_t prepare_scan_kernels();
 hipError_t launch_stage2(const Geometry& g, uint32_t groups, uint32_t q, const uint8_t* partials,
                          uint8_t* out, hipStream_t s);
+// words[i] = a 32-bit hash of (seed, i): stand-in selection bits for the
+// autotuner's timing runs (a scan's duration depends on how many of its
+// operand bits toggle, so a constant fill times it too fast)
+hipError_t launch_fill_hash(uint32_t* dst, uint64_t words, uint64_t seed, hipStream_t s);
 // natural row-major records [rec0, rec0 + nrec) -> bit-sliced blocks starting at rec0 / 32
 hipError_t launch_slice(const Geometry& g, const uint8_t* src, uint64_t nrec, uint32_t* dst_block0,
                         uint64_t nblk, hipStream_t s);

@@ -1285,6 +1285,24 @@ hipError_t launch_stage1_valu(const Geometry& g, const Plan& p, const void* db, 
     return hipErrorInvalidValue;
 }
 
+// SplitMix64's output function over a counter (Steele, Lea and Flood, 2014)
+__global__ void __launch_bounds__(kThreads) k_fill_hash(uint32_t* __restrict__ dst, uint64_t words, uint64_t seed) {
+    const uint64_t step = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += step) {
+        uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        dst[i] = (uint32_t)(z ^ (z >> 31));
+    }
+}
+
+hipError_t launch_fill_hash(uint32_t* dst, uint64_t words, uint64_t seed, hipStream_t s) {
+    if (words == 0) return hipSuccess;
+    const uint64_t blocks = std::min<uint64_t>((words + kThreads - 1) / kThreads, 4096);
+    hipLaunchKernelGGL(k_fill_hash, dim3((uint32_t)blocks), dim3(kThreads), 0, s, dst, words, seed);
+    return hipGetLastError();
+}
+
 hipError_t launch_stage2(const Geometry& g, uint32_t groups, uint32_t q, const uint8_t* partials,
                          uint8_t* out, hipStream_t s) {
     const uint32_t words = q * (g.rpad / 4);

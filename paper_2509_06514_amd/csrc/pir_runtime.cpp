@@ -915,14 +915,20 @@ int pir_tune(pir_db* d, uint32_t q, pir_kernel_cfg* out) {
         }
     }
     if (all.empty()) return fail(PIR_E_INVAL, "pir_tune: no candidate kernels");
-    // scratch selections (content does not affect timing: the scan is oblivious)
-    const uint64_t stride = 4ull * g.nb;
+    // rows at the 256-byte pitch the synchronous calls use (the split-K
+    // kernels' wide selection loads need 16-byte row starts)
+    const uint64_t stride = (4ull * g.nb + 255) / 256 * 256;
     DevBuf sel, outb;
     hipError_t e;
     if ((e = sel.ensure(stride * q)) != hipSuccess) return hip_fail(e, "tune selections");
     if ((e = outb.ensure((size_t)g.R * q)) != hipSuccess) return hip_fail(e, "tune output");
     hipStream_t s = db->ctx_stream;
-    if ((e = hipMemsetAsync(sel.ptr, 0x5A, stride * q, s)) != hipSuccess) return hip_fail(e, "tune memset");
+    // scratch selections of random-looking bits: the scan reads the same bytes
+    // whatever they hold, but its matrix and vector units draw power by the
+    // bits that toggle, and the clock follows (about 5 % between a constant
+    // fill and random bits at Q = 64)
+    if ((e = launch_fill_hash((uint32_t*)sel.ptr, stride * q / 4, 0x5EED0F5E1EC7ull, s)) != hipSuccess)
+        return hip_fail(e, "tune selections fill");
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
         return fail(PIR_E_DEVICE, "event create");

@@ -321,7 +321,7 @@ def test_wide_selection_kernel_unaligned_rows(ctx, n, r):
     q = 64
     sel = synth.selections(n, q, seed=0x16B + n, stride=stride)
     want = oracle.dpxor_batch(dbh, sel)
-    cfgs = [pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 15, 0), pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 16, 0)]
+    cfgs = [pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, u, 0) for u in (15, 16)]
     d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
     for cfg in cfgs:
         for base in (0, 4):
