@@ -193,7 +193,9 @@ int pir_get_cfg(pir_db* db, uint32_t q, pir_kernel_cfg* out);
 
 /*
  * Autotuner: times each candidate configuration for q queries on this
- * database (device-resident scratch selections), keeps the fastest in the
+ * database (device-resident scratch selections of random-looking bits at a
+ * 256-byte row pitch: the scan's time depends on the bits it multiplies,
+ * not only on the bytes it reads), keeps the fastest in the
  * context's cache, keyed by (architecture, R, Q bucket, N bucket), and
  * writes the cache to the JSON file named by the PIR_TUNE_CACHE environment
  * variable if set.  Returns the chosen configuration in *out (may be NULL).

@@ -456,6 +456,103 @@ __device__ __forceinline__ void lds_read_ks(uint32_t b, uint32_t a, u32x4 (&bw)[
         : "v"(b), "v"(a));
 }
 
+// ---- the contraction of one K-step of the split-K kernels, in issue order
+//
+// A wave's K-step is 64 products (2 sub-steps x 4 row tiles x 8 column
+// tiles).  Each operand word is spread into E2M1 values by four "pieces"
+// (spread_fp4_a/b: three masks and one shift-and-mask).  An in-order wave can
+// issue vector-ALU work while the matrix core runs its previous product, but
+// not ahead of a product it is waiting to issue, so the pieces are laid out
+// between the products: the first sub-step's selection operands and its
+// first database operand come first; then, column tile by column tile, each
+// product is followed by one or two pieces of the operands the later
+// products need (the next column tile of this sub-step, then the second
+// sub-step's operands).  Scheduling barriers keep the compiler to this order.
+
+// Spread operands of one K-step: a[sl][rt] (selection, row tile rt) and
+// b[sl][t] (database, column tile t) for sub-step sl, E2M1 in four dwords.
+struct KswOps {
+    i32x4 a[2][4];
+    i32x4 b[2][8];
+};
+
+__device__ __forceinline__ i32x8 widen(const i32x4& x) { return i32x8{x[0], x[1], x[2], x[3], 0, 0, 0, 0}; }
+
+// piece P of spread_fp4_a / spread_fp4_b
+template <int P>
+__device__ __forceinline__ int32_t piece_a(uint32_t w) {
+    if constexpr (P == 0) return (int32_t)(w & 0x11111111u);
+    else if constexpr (P == 1) return (int32_t)(w & 0x22222222u);
+    else if constexpr (P == 2) return (int32_t)(w & 0x44444444u);
+    else return (int32_t)((w >> 1) & 0x44444444u);
+}
+template <int P>
+__device__ __forceinline__ int32_t piece_b(uint32_t w) {
+    if constexpr (P == 0) return (int32_t)(w & 0x44444444u);
+    else if constexpr (P == 1) return (int32_t)(w & 0x22222222u);
+    else if constexpr (P == 2) return (int32_t)(w & 0x11111111u);
+    else return (int32_t)((w >> 3) & 0x11111111u);
+}
+
+// piece I (0..19) of sub-step SL's first operands: the selection operand of
+// row tile I / 4 (I < 16), else the database operand of column tile 0
+template <int SL, int I>
+__device__ __forceinline__ void pro_piece(KswOps& o, const u32x4 (&bw)[4], const u32x2 (&aw)[4]) {
+    if constexpr (I < 16) o.a[SL][I / 4][I % 4] = piece_a<I % 4>(aw[I / 4][SL]);
+    else o.b[SL][0][I % 4] = piece_b<I % 4>(bw[2 * SL][0]);
+}
+// piece P of the database operand of sub-step SL, column tile T
+template <int SL, int T, int P>
+__device__ __forceinline__ void b_piece(KswOps& o, const u32x4 (&bw)[4]) {
+    o.b[SL][T][P] = piece_b<P>(bw[2 * SL + (T >> 2)][T & 3]);
+}
+template <int SL, int I>
+__device__ __forceinline__ void pro_all(KswOps& o, const u32x4 (&bw)[4], const u32x2 (&aw)[4]) {
+    if constexpr (I < 20) {
+        pro_piece<SL, I>(o, bw, aw);
+        pro_all<SL, I + 1>(o, bw, aw);
+    }
+}
+// piece K (0..5) issued among the first sub-step's products of column tile
+// T: the next database operand (K < 4, T < 7), else the second sub-step's
+// first operands
+template <int T, int K>
+__device__ __forceinline__ void group_piece(KswOps& o, const u32x4 (&bw)[4], const u32x2 (&aw)[4]) {
+    if constexpr (T < 7 && K < 4) b_piece<0, T + 1, K>(o, bw);
+    else if constexpr (T < 7) pro_piece<1, 2 * T + (K - 4)>(o, bw, aw);
+    else pro_piece<1, 14 + K>(o, bw, aw);
+}
+
+// product M (sub-step M / 32, column tile M % 32 / 4, row tile M % 4), then
+// its pieces: 2, 1, 2, 1 per column tile in the first sub-step, one (the next
+// database operand's) in the second
+template <int M>
+__device__ __forceinline__ void ksw_sched(f32x4 (&acc)[4][8], KswOps& o, const u32x4 (&bw)[4], const u32x2 (&aw)[4]) {
+    if constexpr (M < 64) {
+        constexpr int sl = M / 32, t = (M % 32) / 4, rt = M % 4;
+        acc[rt][t] = mfma_fp4(widen(o.a[sl][rt]), widen(o.b[sl][t]), acc[rt][t]);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (sl == 0) {
+            constexpr int k0 = rt == 0 ? 0 : rt == 1 ? 2 : rt == 2 ? 3 : 5;
+            group_piece<t, k0>(o, bw, aw);
+            if constexpr (rt == 0 || rt == 2) group_piece<t, k0 + 1>(o, bw, aw);
+        } else if constexpr (t < 7) {
+            b_piece<1, t + 1, rt>(o, bw);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        ksw_sched<M + 1>(acc, o, bw, aw);
+    }
+}
+
+// acc[rt][t] += the K-step whose words are bw (database: bw[2*sl + half] for
+// sub-step sl, columns 64*half + 4j ..) and aw (selection: aw[rt][sl])
+__device__ __forceinline__ void ksw_step_sched(f32x4 (&acc)[4][8], const u32x4 (&bw)[4], const u32x2 (&aw)[4]) {
+    KswOps o;
+    pro_all<0, 0>(o, bw, aw);
+    __builtin_amdgcn_sched_barrier(0);
+    ksw_sched<0>(acc, o, bw, aw);
+}
+
 // Split-K matrix-core scan (fp4, 64-query tiles).  The spread of an operand
 // word costs vector-ALU issue slots that the matrix cores then lose, and a
 // wave spreads (row tiles + column tiles) words per sub-step for
@@ -534,21 +631,7 @@ k_stage1_mfma_ks(const uint32_t* __restrict__ db, const uint32_t* __restrict__ s
 
     // bw[2*sl + half]: sub-step 2h + sl, columns 128c + 64*half + 4j .. +3;
     // aw[rt][sl]: selection word of row 16rt + j for that sub-step
-    auto mma = [&](const u32x4 bw[4], const u32x2 aw[MT]) {
-#pragma unroll
-        for (int sl = 0; sl < 2; ++sl) {
-            i32x8 bx[NT];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) bx[t] = spread_fp4_b(bw[2 * sl + (t >> 2)][t & 3]);
-#pragma unroll
-            for (int rt = 0; rt < MT; ++rt) {
-                const i32x8 ax = spread_fp4_a(aw[rt][sl]);
-#pragma unroll
-                for (int t = 0; t < NT; ++t)
-                    acc[rt][t] = mfma_fp4(ax, bx[t], acc[rt][t]);
-            }
-        }
-    };
+    auto mma = [&](const u32x4 (&bw)[4], const u32x2 (&aw)[MT]) { ksw_step_sched(acc, bw, aw); };
     const uint32_t rd_db =
         (uint32_t)(uintptr_t)(ring_db + (4 * g + 2 * h) * 1024 + (128 * c + 4 * j) * 4);
     const uint32_t rd_sel = (uint32_t)(uintptr_t)(ring_sel + j * 64 + (4 * g + 2 * h) * 4);
@@ -678,103 +761,6 @@ __device__ __forceinline__ void lds_read_ksw(uint32_t b, uint32_t a, u32x4 (&bw)
         : "v"(b), "v"(a));
 }
 static_assert(4 * kWsRowGroup == 4352, "row-tile offset in lds_read_ksw");
-
-// ---- the contraction of one K-step of the split-K kernels, in issue order
-//
-// A wave's K-step is 64 products (2 sub-steps x 4 row tiles x 8 column
-// tiles).  Each operand word is spread into E2M1 values by four "pieces"
-// (spread_fp4_a/b: three masks and one shift-and-mask).  An in-order wave can
-// issue vector-ALU work while the matrix core runs its previous product, but
-// not ahead of a product it is waiting to issue, so the pieces are laid out
-// between the products: the first sub-step's selection operands and its
-// first database operand come first; then, column tile by column tile, each
-// product is followed by one or two pieces of the operands the later
-// products need (the next column tile of this sub-step, then the second
-// sub-step's operands).  Scheduling barriers keep the compiler to this order.
-
-// Spread operands of one K-step: a[sl][rt] (selection, row tile rt) and
-// b[sl][t] (database, column tile t) for sub-step sl, E2M1 in four dwords.
-struct KswOps {
-    i32x4 a[2][4];
-    i32x4 b[2][8];
-};
-
-__device__ __forceinline__ i32x8 widen(const i32x4& x) { return i32x8{x[0], x[1], x[2], x[3], 0, 0, 0, 0}; }
-
-// piece P of spread_fp4_a / spread_fp4_b
-template <int P>
-__device__ __forceinline__ int32_t piece_a(uint32_t w) {
-    if constexpr (P == 0) return (int32_t)(w & 0x11111111u);
-    else if constexpr (P == 1) return (int32_t)(w & 0x22222222u);
-    else if constexpr (P == 2) return (int32_t)(w & 0x44444444u);
-    else return (int32_t)((w >> 1) & 0x44444444u);
-}
-template <int P>
-__device__ __forceinline__ int32_t piece_b(uint32_t w) {
-    if constexpr (P == 0) return (int32_t)(w & 0x44444444u);
-    else if constexpr (P == 1) return (int32_t)(w & 0x22222222u);
-    else if constexpr (P == 2) return (int32_t)(w & 0x11111111u);
-    else return (int32_t)((w >> 3) & 0x11111111u);
-}
-
-// piece I (0..19) of sub-step SL's first operands: the selection operand of
-// row tile I / 4 (I < 16), else the database operand of column tile 0
-template <int SL, int I>
-__device__ __forceinline__ void pro_piece(KswOps& o, const u32x4 (&bw)[4], const u32x2 (&aw)[4]) {
-    if constexpr (I < 16) o.a[SL][I / 4][I % 4] = piece_a<I % 4>(aw[I / 4][SL]);
-    else o.b[SL][0][I % 4] = piece_b<I % 4>(bw[2 * SL][0]);
-}
-// piece P of the database operand of sub-step SL, column tile T
-template <int SL, int T, int P>
-__device__ __forceinline__ void b_piece(KswOps& o, const u32x4 (&bw)[4]) {
-    o.b[SL][T][P] = piece_b<P>(bw[2 * SL + (T >> 2)][T & 3]);
-}
-template <int SL, int I>
-__device__ __forceinline__ void pro_all(KswOps& o, const u32x4 (&bw)[4], const u32x2 (&aw)[4]) {
-    if constexpr (I < 20) {
-        pro_piece<SL, I>(o, bw, aw);
-        pro_all<SL, I + 1>(o, bw, aw);
-    }
-}
-// piece K (0..5) issued among the first sub-step's products of column tile
-// T: the next database operand (K < 4, T < 7), else the second sub-step's
-// first operands
-template <int T, int K>
-__device__ __forceinline__ void group_piece(KswOps& o, const u32x4 (&bw)[4], const u32x2 (&aw)[4]) {
-    if constexpr (T < 7 && K < 4) b_piece<0, T + 1, K>(o, bw);
-    else if constexpr (T < 7) pro_piece<1, 2 * T + (K - 4)>(o, bw, aw);
-    else pro_piece<1, 14 + K>(o, bw, aw);
-}
-
-// product M (sub-step M / 32, column tile M % 32 / 4, row tile M % 4), then
-// its pieces: 2, 1, 2, 1 per column tile in the first sub-step, one (the next
-// database operand's) in the second
-template <int M>
-__device__ __forceinline__ void ksw_sched(f32x4 (&acc)[4][8], KswOps& o, const u32x4 (&bw)[4], const u32x2 (&aw)[4]) {
-    if constexpr (M < 64) {
-        constexpr int sl = M / 32, t = (M % 32) / 4, rt = M % 4;
-        acc[rt][t] = mfma_fp4(widen(o.a[sl][rt]), widen(o.b[sl][t]), acc[rt][t]);
-        __builtin_amdgcn_sched_barrier(0);
-        if constexpr (sl == 0) {
-            constexpr int k0 = rt == 0 ? 0 : rt == 1 ? 2 : rt == 2 ? 3 : 5;
-            group_piece<t, k0>(o, bw, aw);
-            if constexpr (rt == 0 || rt == 2) group_piece<t, k0 + 1>(o, bw, aw);
-        } else if constexpr (t < 7) {
-            b_piece<1, t + 1, rt>(o, bw);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        ksw_sched<M + 1>(acc, o, bw, aw);
-    }
-}
-
-// acc[rt][t] += the K-step whose words are bw (database: bw[2*sl + half] for
-// sub-step sl, columns 64*half + 4j ..) and aw (selection: aw[rt][sl])
-__device__ __forceinline__ void ksw_step_sched(f32x4 (&acc)[4][8], const u32x4 (&bw)[4], const u32x2 (&aw)[4]) {
-    KswOps o;
-    pro_all<0, 0>(o, bw, aw);
-    __builtin_amdgcn_sched_barrier(0);
-    ksw_sched<0>(acc, o, bw, aw);
-}
 
 // The database loads and the K-half fold are those of k_stage1_mfma_ks<2>;
 // the contraction is ksw_step_sched.  Selection stage 0 is loaded before the
