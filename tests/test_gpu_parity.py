@@ -230,6 +230,32 @@ def test_mfma_variants(ctx, variant, n, r):
     db.free()
 
 
+@pytest.mark.parametrize("r", [32, 64])
+def test_split_k_step_counts(ctx, r):
+    # The split-K kernels move selection words in stages of four K-steps (16
+    # blocks of 32 records each) and keep database stages one step ahead:
+    # record groups of exactly 1 .. 9 K-steps (partial last stages), with and
+    # without a ragged tail of fewer than 16 blocks, and a second, partial
+    # 64-query tile, one record group each, all against the oracle.
+    for steps in range(1, 10):
+        for extra in (0, 37 + 32 * 5):
+            n = 512 * steps + extra
+            dbh = synth.database(n, r, seed=0x5C0 + 16 * steps + r + extra)
+            db = ctx.load_db(dbh)
+            sel = synth.selections(n, 70, seed=0x5C1 + steps + extra)
+            want = oracle.dpxor_batch(dbh, sel)
+            d_sel, stride = _dev_rows(sel, n)
+            for q in (64, 70):
+                d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
+                for unroll in (12, 15, 16):
+                    d_out.fill_(0xEE)
+                    db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride,
+                                         cfg=pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, unroll, 1))
+                    torch.cuda.synchronize()
+                    assert np.array_equal(d_out.cpu().numpy(), want[:q]), (steps, extra, q, unroll)
+            db.free()
+
+
 @pytest.mark.parametrize("variant", MFMA_VARIANTS)
 def test_mfma_counts_exact_on_large_group(ctx, variant):
     # 2^25 records: one requested record group would hold 2^25 > 2^24 records;
