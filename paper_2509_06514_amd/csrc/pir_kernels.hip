@@ -829,9 +829,11 @@ k_stage1_mfma_ksw(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
     auto issue_sel = [&](uint32_t m, int st) {
         uint32_t off = sel_off[st];
         if (4 * m + 3 >= nsteps && 4 * m + (ch >> 2) >= nsteps) off -= 16 * (ch & ~3u);
+        // whole lines of each row, read once: nontemporal (the 4-byte loads
+        // of the ring kernels take half a line per step and keep the default)
         __builtin_amdgcn_global_load_lds(
             reinterpret_cast<const uint32_t*>(uniform_ptr(sel_row[st] + (uint64_t)m * 256) + off),
-            ring_sel + (m & 1) * kSelStage + (4 * st + wave) * RG, 16, 0, 0);
+            ring_sel + (m & 1) * kSelStage + (4 * st + wave) * RG, 16, 0, 2);
     };
 
     f32x4 acc[MT][NT];
@@ -1002,9 +1004,10 @@ k_stage1_mfma_ksp(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
         for (int st = 0; st < 4; ++st) {
             uint32_t off = sel_off[st];
             if (4 * m + 3 >= nsteps && 4 * m + (ch >> 2) >= nsteps) off -= 16 * (ch & ~3u);
+            // whole lines of each row, read once: nontemporal
             __builtin_amdgcn_global_load_lds(
                 reinterpret_cast<const uint32_t*>(uniform_ptr(sel_row[st] + (uint64_t)m * 256) + off),
-                ring_sel + (m & 1) * kSelStage + (4 * st + wave) * RG, 16, 0, 0);
+                ring_sel + (m & 1) * kSelStage + (4 * st + wave) * RG, 16, 0, 2);
         }
     };
 
