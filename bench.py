@@ -82,20 +82,23 @@ def kernel_source_hash(srcs=SCAN_SOURCES):
     return h.hexdigest()[:16]
 
 
-def kernel_name(cfg, r):
-    """Name of the stage-1 kernel instance a plan launches (as profilers print it)."""
+def kernel_name(cfg, r, q=64):
+    """Name of the stage-1 kernel instance a plan launches for q queries (as profilers
+    print it). The split-K kernels' second template argument is the database loads'
+    cache policy: 2 (nontemporal) for one 64-query tile, 0 for several."""
     if cfg.variant == 1:
         return f"k_stage1_valu<{cfg.q_tile}, {cfg.unroll}, {'true' if r < 32 else 'false'}>"
     mt = cfg.q_tile // 16
     f4 = "true" if cfg.variant == 3 else "false"
     if cfg.unroll in (2, 3, 4):  # LDS ring of that many stages
         return f"k_stage1_mfma_lds<{mt}, {f4}, {cfg.unroll}>"
+    dbp = 0 if (q + cfg.q_tile - 1) // cfg.q_tile > 1 else 2
     if cfg.unroll == 12:  # split K on a 2-stage ring
-        return "k_stage1_mfma_ks<2>"
+        return f"k_stage1_mfma_ks<2, {dbp}>"
     if cfg.unroll == 15:  # split K, 2-stage ring, selection words 4 K-steps at a time
-        return "k_stage1_mfma_ksw"
+        return f"k_stage1_mfma_ksw<{dbp}>"
     if cfg.unroll == 16:  # the same with wave-private database stages
-        return "k_stage1_mfma_ksp"
+        return f"k_stage1_mfma_ksp<{dbp}>"
     return None
 
 
@@ -111,7 +114,7 @@ def load_traffic(n, r, q, cfg):
     entry = t.get(f"q{q}")
     if not entry or t.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    if entry.get("kernel") != kernel_name(cfg, r):
+    if entry.get("kernel") != kernel_name(cfg, r, q):
         return None
     return entry.get("hbm_bytes_per_launch")
 

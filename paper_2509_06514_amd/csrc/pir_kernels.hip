@@ -567,7 +567,7 @@ __device__ __forceinline__ void ksw_step_sched(f32x4 (&acc)[4][8], const u32x4 (
 // address is a wave-uniform base plus a fixed 32-bit lane offset; the
 // selection offsets span three rows, which bounds the selection pitch
 // (checked by the launcher).
-template <int S>
+template <int S, int DBP>
 __global__ void __launch_bounds__(kThreads)
 k_stage1_mfma_ks(const uint32_t* __restrict__ db, const uint32_t* __restrict__ sel,
                  uint8_t* __restrict__ partials, Stage1Params p) {
@@ -614,7 +614,7 @@ k_stage1_mfma_ks(const uint32_t* __restrict__ db, const uint32_t* __restrict__ s
             const uint32_t b = 4 * i + wave;
             const uint8_t* base = uniform_ptr(db_tile + (kb + b) * block_words * 4);
             __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint32_t*>(base + db_off),
-                                             dst_db + b * 1024, 16, 0, 2);
+                                             dst_db + b * 1024, 16, 0, DBP);
         }
 #pragma unroll
         for (int i = 0; i < MT; ++i)
@@ -769,6 +769,7 @@ static_assert(4 * kWsRowGroup == 4352, "row-tile offset in lds_read_ksw");
 // stage load no selection words.  Each step waits for all of its wave's
 // earlier loads and then meets the others at a barrier, as in the 2-stage
 // ring.
+template <int DBP>
 __global__ void __launch_bounds__(kThreads)
 k_stage1_mfma_ksw(const uint32_t* __restrict__ db, const uint32_t* __restrict__ sel,
                   uint8_t* __restrict__ partials, Stage1Params p) {
@@ -802,9 +803,11 @@ k_stage1_mfma_ksw(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
             const uint32_t b = 4 * i + wave;
             const uint8_t* base =
                 uniform_ptr(db_tile + (b_begin + (uint64_t)k * kMfmaBlocksPerStep + b) * block_words * 4);
-            // database chunks are read once: nontemporal (cache policy NT = 2)
+            // cache policy DBP: nontemporal (2) when one query tile reads each
+            // database chunk once, default (0) when several tiles' workgroups
+            // read it in turn through L2
             __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint32_t*>(base + db_off), dst + b * 1024, 16,
-                                             0, 2);
+                                             0, DBP);
         }
     };
 
@@ -944,6 +947,7 @@ k_stage1_mfma_ksw(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
 // once per stage.
 constexpr uint32_t kSpLdsBytes = 2 * kWsStageSelBytes + 4 * 2 * 4096;
 
+template <int DBP>
 __global__ void __launch_bounds__(kThreads)
 k_stage1_mfma_ksp(const uint32_t* __restrict__ db, const uint32_t* __restrict__ sel,
                   uint8_t* __restrict__ partials, Stage1Params p) {
@@ -977,9 +981,9 @@ k_stage1_mfma_ksp(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
         for (int i = 0; i < 4; ++i) {
             const uint8_t* base =
                 uniform_ptr(db_wave + ((uint64_t)k * kMfmaBlocksPerStep + 4 * i) * block_words * 4);
-            // database chunks are read once: nontemporal (cache policy NT = 2)
+            // cache policy DBP, as in k_stage1_mfma_ksw
             __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint32_t*>(base + db_lane), dst + i * 1024, 16,
-                                             0, 2);
+                                             0, DBP);
         }
     };
 
@@ -1350,15 +1354,29 @@ static hipError_t launch_ring(dim3 grid, hipStream_t s, const uint32_t* db, cons
 // offsets, up to three rows plus 60 bytes, fit in 32 bits.
 constexpr uint64_t kKsMaxStrideWords = ((1ull << 32) - 64) / 12;
 
+// Database cache policy of the split-K kernels: nontemporal (2) when the
+// launch has one query tile, so that each database chunk is read once;
+// default (0) when several query tiles' workgroups read each chunk in turn
+// (they run on one XCD and meet in its L2: at Q = 512 on 8 GiB the
+// nontemporal policy fetched 1.32x the algorithmic bytes, the default 1.00x)
+static bool db_shared_by_tiles(const Stage1Params& p) { return p.n_qt > 1; }
+
+template <int S, int DBP>
+static hipError_t launch_ks_p(dim3 grid, hipStream_t s, const uint32_t* db, const uint32_t* sel, uint8_t* partials,
+                              const Stage1Params& p) {
+    constexpr uint32_t bytes = ring_bytes<4>(S);
+    const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ks<S, DBP>), (int)bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_stage1_mfma_ks<S, DBP>), grid, dim3(kThreads), bytes, s, db, sel, partials, p);
+    return hipGetLastError();
+}
+
 template <int S>
 static hipError_t launch_ks(dim3 grid, hipStream_t s, const uint32_t* db, const uint32_t* sel, uint8_t* partials,
                             const Stage1Params& p) {
     if (p.stride_words > kKsMaxStrideWords) return launch_ring<4, true, S>(grid, s, db, sel, partials, p);
-    constexpr uint32_t bytes = ring_bytes<4>(S);
-    const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ks<S>), (int)bytes);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_stage1_mfma_ks<S>), grid, dim3(kThreads), bytes, s, db, sel, partials, p);
-    return hipGetLastError();
+    return db_shared_by_tiles(p) ? launch_ks_p<S, 0>(grid, s, db, sel, partials, p)
+                                 : launch_ks_p<S, 2>(grid, s, db, sel, partials, p);
 }
 
 // The split-K kernels with wide selection loads move 16 bytes per lane: rows
@@ -1369,22 +1387,36 @@ static bool wide_sel_ok(const uint32_t* sel, const Stage1Params& p) {
            (reinterpret_cast<uintptr_t>(sel) & 15) == 0;
 }
 
+template <int DBP>
+static hipError_t launch_ksw_p(dim3 grid, hipStream_t s, const uint32_t* db, const uint32_t* sel, uint8_t* partials,
+                               const Stage1Params& p) {
+    const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksw<DBP>), (int)kWsLdsBytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_stage1_mfma_ksw<DBP>, grid, dim3(kThreads), kWsLdsBytes, s, db, sel, partials, p);
+    return hipGetLastError();
+}
+
 static hipError_t launch_ksw(dim3 grid, hipStream_t s, const uint32_t* db, const uint32_t* sel, uint8_t* partials,
                              const Stage1Params& p) {
     if (!wide_sel_ok(sel, p)) return launch_ks<2>(grid, s, db, sel, partials, p);
-    const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksw), (int)kWsLdsBytes);
+    return db_shared_by_tiles(p) ? launch_ksw_p<0>(grid, s, db, sel, partials, p)
+                                 : launch_ksw_p<2>(grid, s, db, sel, partials, p);
+}
+
+template <int DBP>
+static hipError_t launch_ksp_p(dim3 grid, hipStream_t s, const uint32_t* db, const uint32_t* sel, uint8_t* partials,
+                               const Stage1Params& p) {
+    const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksp<DBP>), (int)kSpLdsBytes);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_stage1_mfma_ksw, grid, dim3(kThreads), kWsLdsBytes, s, db, sel, partials, p);
+    hipLaunchKernelGGL(k_stage1_mfma_ksp<DBP>, grid, dim3(kThreads), kSpLdsBytes, s, db, sel, partials, p);
     return hipGetLastError();
 }
 
 static hipError_t launch_ksp(dim3 grid, hipStream_t s, const uint32_t* db, const uint32_t* sel, uint8_t* partials,
                              const Stage1Params& p) {
     if (!wide_sel_ok(sel, p)) return launch_ks<2>(grid, s, db, sel, partials, p);
-    const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksp), (int)kSpLdsBytes);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_stage1_mfma_ksp, grid, dim3(kThreads), kSpLdsBytes, s, db, sel, partials, p);
-    return hipGetLastError();
+    return db_shared_by_tiles(p) ? launch_ksp_p<0>(grid, s, db, sel, partials, p)
+                                 : launch_ksp_p<2>(grid, s, db, sel, partials, p);
 }
 
 template <int MT, bool F4>
@@ -1441,9 +1473,12 @@ hipError_t prepare_scan_kernels() {
     if ((e = prepare_rings<1, true>()) || (e = prepare_rings<2, true>()) || (e = prepare_rings<4, true>()) ||
         (e = prepare_rings<1, false>()) || (e = prepare_rings<2, false>()) || (e = prepare_rings<4, false>()))
         return e;
-    if ((e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ks<2>), (int)ring_bytes<4>(2))) ||
-        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksw), (int)kWsLdsBytes)) ||
-        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksp), (int)kSpLdsBytes)))
+    if ((e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ks<2, 0>), (int)ring_bytes<4>(2))) ||
+        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ks<2, 2>), (int)ring_bytes<4>(2))) ||
+        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksw<0>), (int)kWsLdsBytes)) ||
+        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksw<2>), (int)kWsLdsBytes)) ||
+        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksp<0>), (int)kSpLdsBytes)) ||
+        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksp<2>), (int)kSpLdsBytes)))
         return e;
     return hipSuccess;
 }

@@ -374,12 +374,10 @@ int Ctx::plan_for(const Db& db, uint32_t q, const pir_kernel_cfg* cfg, Plan& p) 
         } else if (q >= 8 && mfma_supported(PIR_VARIANT_MFMA_F4, db.geo, 16, 4)) {
             // untuned: from 8 queries up the fp4 matrix cores, as the tuner
             // picks on MI355X; for 64-query tiles the split-K kernel with
-            // wave-private database stages up to four tiles, with shared
-            // stages (whose database reads the tiles' workgroups share
-            // through L2 in step) beyond
+            // wave-private database stages
             base.variant = PIR_VARIANT_MFMA_F4;
             base.qt = q <= 16 ? 16 : (q <= 32 ? 32 : 64);
-            base.unroll = base.qt == 64 ? (q <= 256 ? 16 : 15) : 4;
+            base.unroll = base.qt == 64 ? 16 : 4;
         } else {
             base.variant = PIR_VARIANT_VALU;
         }

@@ -20,20 +20,23 @@ def test_more_than_one_gpu_exits_with_a_message():
     assert "one GPU only" in (r.stdout + r.stderr)
 
 
-@pytest.mark.parametrize("cfg,r,name", [
-    ((1, 1, 8, 0), 32, "k_stage1_valu<1, 8, false>"),
-    ((1, 8, 2, 0), 16, "k_stage1_valu<8, 2, true>"),
-    ((3, 64, 3, 0), 32, "k_stage1_mfma_lds<4, true, 3>"),
-    ((2, 16, 4, 0), 32, "k_stage1_mfma_lds<1, false, 4>"),
-    ((3, 64, 12, 0), 32, "k_stage1_mfma_ks<2>"),
-    ((3, 64, 15, 0), 32, "k_stage1_mfma_ksw"),
-    ((3, 64, 16, 0), 32, "k_stage1_mfma_ksp"),
+@pytest.mark.parametrize("cfg,r,q,name", [
+    ((1, 1, 8, 0), 32, 1, "k_stage1_valu<1, 8, false>"),
+    ((1, 8, 2, 0), 16, 8, "k_stage1_valu<8, 2, true>"),
+    ((3, 64, 3, 0), 32, 64, "k_stage1_mfma_lds<4, true, 3>"),
+    ((2, 16, 4, 0), 32, 16, "k_stage1_mfma_lds<1, false, 4>"),
+    ((3, 64, 12, 0), 32, 64, "k_stage1_mfma_ks<2, 2>"),
+    ((3, 64, 15, 0), 32, 64, "k_stage1_mfma_ksw<2>"),
+    ((3, 64, 16, 0), 32, 64, "k_stage1_mfma_ksp<2>"),
+    ((3, 64, 15, 0), 32, 512, "k_stage1_mfma_ksw<0>"),
+    ((3, 64, 16, 0), 256, 256, "k_stage1_mfma_ksp<0>"),
+    ((3, 64, 12, 0), 32, 65, "k_stage1_mfma_ks<2, 0>"),
 ])
-def test_kernel_names_follow_the_plan(cfg, r, name):
-    assert bench.kernel_name(pir.KernelCfg(*cfg), r) == name
+def test_kernel_names_follow_the_plan(cfg, r, q, name):
+    assert bench.kernel_name(pir.KernelCfg(*cfg), r, q) == name
 
 
 def test_kernel_names_exist_in_the_source():
     src = open(os.path.join(ROOT, "paper_2509_06514_amd", "csrc", "pir_kernels.hip")).read()
-    for kernel in ("k_stage1_valu", "k_stage1_mfma_lds", "k_stage1_mfma_ks", "k_stage1_mfma_ksw"):
+    for kernel in ("k_stage1_valu", "k_stage1_mfma_lds", "k_stage1_mfma_ks", "k_stage1_mfma_ksw", "k_stage1_mfma_ksp"):
         assert f"\n{kernel}(" in src, kernel
