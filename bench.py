@@ -119,6 +119,25 @@ def load_traffic(n, r, q, cfg):
     return entry.get("hbm_bytes_per_launch")
 
 
+def sample_engine_clock(period_s, stop, out):
+    """Append the current engine clock (MHz, the starred level of sysfs
+    pp_dpm_sclk) to `out` every period_s seconds until `stop` is set."""
+    import glob
+    paths = glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk")
+    if not paths:
+        log("serve: no pp_dpm_sclk; engine clock not sampled")
+        return
+    while not stop.is_set():
+        try:
+            with open(paths[0]) as f:
+                for line in f:
+                    if line.rstrip().endswith("*"):
+                        out.append(int(line.split(":")[1].strip().lower().split("mhz")[0]))
+        except (OSError, ValueError):
+            pass
+        stop.wait(period_s)
+
+
 def percentile(xs, f):
     s = sorted(xs)
     k = min(len(s) - 1, max(0, int(round(f * (len(s) - 1)))))
@@ -647,11 +666,21 @@ def serve_bench(args):
                 k += 1
 
         ths = [threading.Thread(target=submitter, args=(i,)) for i in range(threads_n)]
+        clock = []
+        clock_stop = threading.Event()
+        if args.serve_clock_ms > 0:
+            ths_clock = threading.Thread(target=sample_engine_clock,
+                                         args=(args.serve_clock_ms / 1e3, clock_stop, clock), daemon=True)
         srv.stats(reset=True)
+        if args.serve_clock_ms > 0:
+            ths_clock.start()
         for th in ths:
             th.start()
         for th in ths:
             th.join()
+        if args.serve_clock_ms > 0:
+            clock_stop.set()
+            ths_clock.join()
         for lst in pending:
             for tk in lst:
                 srv.wait(tk, 60000)
@@ -674,6 +703,11 @@ def serve_bench(args):
                "max_ms": st["max_us"] / 1e3,
                "batches": st["batches"], "batch_hist": hist, "max_inflight": st["max_inflight"],
                "h2d_GBps": st["h2d_bytes"] / dur / 1e9}
+        if clock:
+            cs = sorted(clock)
+            rec["engine_clock_mhz"] = {"samples": len(cs), "median": cs[len(cs) // 2], "p10": cs[len(cs) // 10],
+                                       "p90": cs[9 * len(cs) // 10], "min": cs[0],
+                                       "below_500": sum(1 for c in cs if c < 500) / len(cs)}
         if check is not None:
             rec["two_server_check"] = bool(check)
         else:
@@ -728,6 +762,9 @@ def main():
     ap.add_argument("--serve-qmax", type=int, default=64)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-wait-us", type=int, default=200)
+    ap.add_argument("--serve-clock-ms", type=float, default=0.0,
+                    help="sample the engine clock (sysfs pp_dpm_sclk) every this many ms while serving; "
+                         "the polling itself can change the device's power states")
     ap.add_argument("--no-read-roof", action="store_true", help="skip the streaming-read roof probe")
     ap.add_argument("--phase-steps", type=int, default=10,
                     help="rounds of the per-phase breakdown (selection upload, stages, answer download; 0 = skip)")
