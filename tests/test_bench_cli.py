@@ -40,3 +40,24 @@ def test_kernel_names_exist_in_the_source():
     src = open(os.path.join(ROOT, "paper_2509_06514_amd", "csrc", "pir_kernels.hip")).read()
     for kernel in ("k_stage1_valu", "k_stage1_mfma_lds", "k_stage1_mfma_ks", "k_stage1_mfma_ksw", "k_stage1_mfma_ksp"):
         assert f"\n{kernel}(" in src, kernel
+
+
+def test_engine_clock_sampler_reads_the_starred_level(tmp_path, monkeypatch):
+    # the serving sweep's optional clock samples come from sysfs pp_dpm_sclk,
+    # whose current level carries a trailing '*'
+    import threading
+    f = tmp_path / "pp_dpm_sclk"
+    f.write_text("S: 96Mhz\n0: 500Mhz\n1: 2243Mhz *\n2: 2400Mhz\n")
+    import glob as glob_mod
+    monkeypatch.setattr(glob_mod, "glob", lambda pattern: [str(f)])
+    stop, out = threading.Event(), []
+    th = threading.Thread(target=bench.sample_engine_clock, args=(0.001, stop, out))
+    th.start()
+    import time
+    deadline = time.time() + 10
+    while len(out) < 3 and time.time() < deadline:
+        time.sleep(0.001)
+    stop.set()
+    th.join(timeout=10)
+    assert not th.is_alive()
+    assert set(out) == {2243}
