@@ -99,6 +99,8 @@ def kernel_name(cfg, r, q=64):
         return f"k_stage1_mfma_ksw<{dbp}>"
     if cfg.unroll == 16:  # the same with wave-private database stages
         return f"k_stage1_mfma_ksp<{dbp}>"
+    if cfg.unroll == 17:  # the same with the database words loaded into registers
+        return f"k_stage1_mfma_ksv<{dbp}>"
     return None
 
 
@@ -332,7 +334,7 @@ def variant_sweep(ctx, db, d_sel, stride, n, r, q, d_out, torch, pir, reps=3):
         for v in (2, 3):
             for qt in (16, 32, 64):
                 if qt <= max(p2, 16):
-                    fams[v] += [(qt, u) for u in (2, 3, 4) + ((15, 16) if v == 3 and qt == 64 else ())]
+                    fams[v] += [(qt, u) for u in (2, 3, 4) + ((15, 16, 17) if v == 3 and qt == 64 else ())]
     ref, same, out = None, True, {}
     for v, cands in fams.items():
         best = None

@@ -179,7 +179,8 @@ typedef struct pir_kernel_cfg {
                          many stages, 12 = split-K kernel on a 2-stage ring (fp4, q_tile 64),
                          15 = split-K kernel on a 2-stage ring whose selection words arrive
                          4 K-steps at a time, 16 = the same with wave-private database
-                         stages (both fp4, q_tile 64); 0 = default */
+                         stages, 17 = the same with the database words loaded straight
+                         into registers (all fp4, q_tile 64); 0 = default */
     uint32_t groups;  /* record groups = partial results per query (0 = default) */
 } pir_kernel_cfg;
 

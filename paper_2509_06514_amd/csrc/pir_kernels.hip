@@ -553,6 +553,19 @@ __device__ __forceinline__ void ksw_step_sched(f32x4 (&acc)[4][8], const u32x4 (
     ksw_sched<0>(acc, o, bw, aw);
 }
 
+// The same K-step with `mid` issued between the first operands' spread and
+// the first product (k_stage1_mfma_ksv issues its next loads there).
+template <class F>
+__device__ __forceinline__ void ksw_step_sched_mid(f32x4 (&acc)[4][8], const u32x4 (&bw)[4], const u32x2 (&aw)[4],
+                                                   F&& mid) {
+    KswOps o;
+    pro_all<0, 0>(o, bw, aw);
+    __builtin_amdgcn_sched_barrier(0);
+    mid();
+    __builtin_amdgcn_sched_barrier(0);
+    ksw_sched<0>(acc, o, bw, aw);
+}
+
 // Split-K matrix-core scan (fp4, 64-query tiles).  The spread of an operand
 // word costs vector-ALU issue slots that the matrix cores then lose, and a
 // wave spreads (row tiles + column tiles) words per sub-step for
@@ -1131,6 +1144,212 @@ k_stage1_mfma_ksp(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
     }
 }
 
+// Split-K kernel with the database words loaded straight into registers.
+// Each wave's database words (its K half, its 128 columns) are used by that
+// wave alone, so instead of staging them through LDS (k_stage1_mfma_ksp) it
+// loads them into the registers the products read, one K-step ahead: no LDS
+// write and read-back per word.  The selection stages stay shared (four
+// K-steps, 256 bytes per row, double-buffered), but they too arrive through
+// registers (the same 16-byte chunks, then written to the stage buffer at
+// the end of the stage before): with no direct-to-LDS load in flight the
+// compiler counts the outstanding loads in order and waits only for the one
+// an operand needs.  The next step's loads are issued after the first
+// operands' spread, behind the compiler's wait for this step's words.
+constexpr uint32_t kSvLdsBytes = 2 * kWsStageSelBytes;
+
+template <int DBP>
+__global__ void __launch_bounds__(kThreads)
+k_stage1_mfma_ksv(const uint32_t* __restrict__ db, const uint32_t* __restrict__ sel,
+                  uint8_t* __restrict__ partials, Stage1Params p) {
+    constexpr int MT = 4, NT = 8, QT = 64;
+    constexpr uint32_t RG = kWsRowGroup, kSelStage = kWsStageSelBytes;
+    extern __shared__ __attribute__((aligned(16))) uint8_t pir_ring[];
+    uint8_t* const ring_sel = pir_ring;
+
+    uint32_t group, ct, qt;
+    if (!decode_block(p.groups, p.n_ct, p.n_qt, group, ct, qt)) return;
+
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t c = wave & 1, h = wave >> 1;
+    const uint32_t j = lane & 15, g = lane >> 4;
+    const uint32_t q0 = qt * QT;
+    const uint64_t block_words = 8ull * p.R;
+    const uint64_t b_begin = (uint64_t)group * p.units_per_group;
+    const uint64_t b_end = (b_begin + p.units_per_group < p.n_units) ? b_begin + p.units_per_group : p.n_units;
+    const uint32_t nsteps = (uint32_t)((b_end - b_begin) / kMfmaBlocksPerStep);
+
+    // database: lane (j, g) takes bw[2*sl + half] = block 4g + 2h + sl of the
+    // step, words 128c + 64*half + 4j .. +3 (the operand layout of
+    // ksw_step_sched); cache policy DBP as in k_stage1_mfma_ksw
+    const u32x4* db_lane = reinterpret_cast<const u32x4*>(db + ct * 256 + (b_begin + 4 * g + 2 * h) * block_words +
+                                                          128 * c + 4 * j);
+    auto load_db = [&](uint32_t k, u32x4 (&w)[4]) {
+        const u32x4* q = db_lane + (uint64_t)k * kMfmaBlocksPerStep * (block_words / 4);
+        if constexpr (DBP == 2) {
+            w[0] = __builtin_nontemporal_load(q);
+            w[1] = __builtin_nontemporal_load(q + 16);
+            w[2] = __builtin_nontemporal_load(q + block_words / 4);
+            w[3] = __builtin_nontemporal_load(q + block_words / 4 + 16);
+        } else {
+            w[0] = q[0];
+            w[1] = q[16];
+            w[2] = q[block_words / 4];
+            w[3] = q[block_words / 4 + 16];
+        }
+    };
+
+    // selection chunks as in k_stage1_mfma_ksw: chunk 4s + w of a stage is
+    // rows q0 + 4(4s + w) .. +3; lane l takes chunk (l & 15) ^ (l >> 4) of
+    // row l >> 4 and stores it at position l & 15 of that row
+    const uint32_t ch = (lane & 15) ^ (lane >> 4);
+    const uint8_t* sel_row[4];
+    uint32_t sel_off[4];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+        uint32_t r0 = q0 + 4 * (4 * st + wave);
+        const bool any = r0 < p.q_total;
+        if (!any) r0 = q0;
+        const uint32_t rl = (any && r0 + lane / 16 < p.q_total) ? lane / 16 : 0;
+        sel_row[st] = reinterpret_cast<const uint8_t*>(sel + (uint64_t)r0 * p.stride_words + b_begin);
+        sel_off[st] = rl * (uint32_t)(p.stride_words * 4) + 16 * ch;
+    }
+    // a chunk of a K-step past the group's last full step re-reads the same
+    // position of the stage's first step (valid, never used); whole lines of
+    // each row, read once: nontemporal
+    auto load_sel = [&](uint32_t m, u32x4 (&sv)[4]) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            uint32_t off = sel_off[st];
+            if (4 * m + 3 >= nsteps && 4 * m + (ch >> 2) >= nsteps) off -= 16 * (ch & ~3u);
+            sv[st] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(sel_row[st] + (uint64_t)m * 256 + off));
+        }
+    };
+    auto store_sel = [&](uint32_t m, const u32x4 (&sv)[4]) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+            *reinterpret_cast<u32x4*>(ring_sel + (m & 1) * kSelStage + (4 * st + wave) * RG + 16 * lane) = sv[st];
+    };
+
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int rt = 0; rt < MT; ++rt)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[rt][t] = f32x4{0, 0, 0, 0};
+
+    auto mma = [&](const u32x4 (&bw)[4], const u32x2 (&aw)[MT]) { ksw_step_sched(acc, bw, aw); };
+    // row 16rt + j, word 16s + 4g + 2h (chunk 4s + g) of stage buffer m & 1
+    const uint32_t rd_sel = (uint32_t)(uintptr_t)(ring_sel + (j >> 2) * RG + (j & 3) * 256 +
+                                                  16 * (g ^ (j & 3)) + 8 * h);
+    auto read_sel = [&](uint32_t a, u32x2 (&aw)[MT]) {
+        asm volatile(
+            "ds_read_b64 %0, %4\n\t"
+            "ds_read_b64 %1, %4 offset:4352\n\t"
+            "ds_read_b64 %2, %4 offset:8704\n\t"
+            "ds_read_b64 %3, %4 offset:13056\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(aw[0]), "=&v"(aw[1]), "=&v"(aw[2]), "=&v"(aw[3])
+            : "v"(a));
+    };
+
+    u32x4 bwc[4], svn[4];
+    if (nsteps > 0) {
+        u32x4 sv0[4];
+        load_sel(0, sv0);
+        store_sel(0, sv0);
+        load_db(0, bwc);
+        load_sel(4 < nsteps ? 1 : 0, svn);
+    }
+    for (uint32_t m = 0; 4 * m < nsteps; ++m) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            const uint32_t k = 4 * m + st;
+            if (k >= nsteps) break;
+            if (st == 0) {
+                // this wave's stores of stage m are done ...
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+                // ... and every wave's; stage m - 1's buffer has been read
+                wg_barrier();
+            }
+            u32x2 aw[MT];
+            read_sel(rd_sel + (m & 1) * kSelStage + 64 * st, aw);
+            u32x4 bwn[4];
+            // the last step re-reads its own words (in bounds, unused), so
+            // that the load is unconditional
+            ksw_step_sched_mid(acc, bwc, aw, [&] { load_db(k + 1 < nsteps ? k + 1 : k, bwn); });
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) bwc[i] = bwn[i];
+            if ((st == 3 || k + 1 == nsteps) && 4 * (m + 1) < nsteps) {
+                // stage m + 1 into the buffer of stage m - 1, which every
+                // wave has read (all passed this stage's barrier)
+                store_sel(m + 1, svn);
+                load_sel(4 * (m + 2) < nsteps ? m + 2 : m + 1, svn);
+            }
+        }
+    }
+    wait_vmcnt<0>();
+
+    // ragged tail (fewer than 16 blocks) straight from memory
+    const uint64_t kb = b_begin + (uint64_t)nsteps * kMfmaBlocksPerStep;
+    if (kb < b_end) {
+        const u32x4* dl = reinterpret_cast<const u32x4*>(db + ct * 256 + 128 * c + 4 * j);
+        u32x4 bw[4];
+        u32x2 aw[MT];
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+            const uint64_t blk = kb + 4 * g + 2 * h + sl;
+            const bool ok = blk < b_end;
+            bw[2 * sl] = ok ? dl[blk * (block_words / 4)] : u32x4{0, 0, 0, 0};
+            bw[2 * sl + 1] = ok ? dl[blk * (block_words / 4) + 16] : u32x4{0, 0, 0, 0};
+#pragma unroll
+            for (int rt = 0; rt < MT; ++rt) {
+                const uint32_t q = q0 + 16 * rt + j;
+                aw[rt][sl] = (ok && q < p.q_total) ? sel[(uint64_t)q * p.stride_words + blk] : 0u;
+            }
+        }
+        mma(bw, aw);
+    }
+
+    // answer bits: lane holds columns 128c + 64*half + 4j + t' of rows
+    // 16rt + 4g + r; bit 8r + 4*half + t' of par[rt]
+    uint32_t par[MT];
+#pragma unroll
+    for (int rt = 0; rt < MT; ++rt) {
+        par[rt] = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) par[rt] |= (((uint32_t)acc[rt][t][r]) & 1u) << (8 * r + t);
+    }
+    // fold the K halves through LDS (every load has landed and, after this
+    // barrier, every wave has read its last stage)
+    __syncthreads();
+    u32x4* fold = reinterpret_cast<u32x4*>(pir_ring) + c * 64 + lane;
+    if (h == 1) *fold = u32x4{par[0], par[1], par[2], par[3]};
+    __syncthreads();  // the fold writes are complete and visible
+    if (h == 1) return;
+    const u32x4 o = *fold;
+    par[0] ^= o[0];
+    par[1] ^= o[1];
+    par[2] ^= o[2];
+    par[3] ^= o[3];
+#pragma unroll
+    for (int rt = 0; rt < MT; ++rt) {
+        const uint32_t other = (uint32_t)__shfl_xor((int)par[rt], 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t q = q0 + 16 * rt + 4 * g + r;
+            const uint32_t mine = par[rt] >> (8 * r), theirs = other >> (8 * r);
+            if ((j & 1) == 0 && q < p.q_total) {
+                uint8_t* dst = partials + ((uint64_t)group * p.q_total + q) * p.rpad + ct * 32 + 16 * c + j / 2;
+                dst[0] = (uint8_t)((mine & 0xF) | ((theirs & 0xF) << 4));
+                dst[8] = (uint8_t)(((mine >> 4) & 0xF) | (theirs & 0xF0));
+            }
+        }
+    }
+}
+
 // Stage 2: out[q][m] = XOR over groups of partials[g][q][m].  Each workgroup
 // owns `wpb` consecutive 32-bit words of the [q][rpad] result (wpb a power of
 // two) and splits the groups over 256 / wpb slices, then folds the slices
@@ -1335,7 +1554,7 @@ bool mfma_supported(uint32_t variant, const Geometry& g, uint32_t qt, uint32_t u
     // 2-stage ring (fp4, 64-query tiles); 15 = the split-K kernel whose
     // selection words arrive four K-steps at a time, 16 = the same with
     // wave-private database stages (both fp4, 64-query tiles)
-    if (unroll == 12 || unroll == 15 || unroll == 16) return variant == PIR_VARIANT_MFMA_F4 && qt == 64;
+    if (unroll == 12 || unroll == 15 || unroll == 16 || unroll == 17) return variant == PIR_VARIANT_MFMA_F4 && qt == 64;
     if (unroll != 2 && unroll != 3 && unroll != 4) return false;
     return qt == 16 || qt == 32 || qt == 64;
 }
@@ -1419,6 +1638,22 @@ static hipError_t launch_ksp(dim3 grid, hipStream_t s, const uint32_t* db, const
                                  : launch_ksp_p<2>(grid, s, db, sel, partials, p);
 }
 
+template <int DBP>
+static hipError_t launch_ksv_p(dim3 grid, hipStream_t s, const uint32_t* db, const uint32_t* sel, uint8_t* partials,
+                               const Stage1Params& p) {
+    const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksv<DBP>), (int)kSvLdsBytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_stage1_mfma_ksv<DBP>, grid, dim3(kThreads), kSvLdsBytes, s, db, sel, partials, p);
+    return hipGetLastError();
+}
+
+static hipError_t launch_ksv(dim3 grid, hipStream_t s, const uint32_t* db, const uint32_t* sel, uint8_t* partials,
+                             const Stage1Params& p) {
+    if (!wide_sel_ok(sel, p)) return launch_ks<2>(grid, s, db, sel, partials, p);
+    return db_shared_by_tiles(p) ? launch_ksv_p<0>(grid, s, db, sel, partials, p)
+                                 : launch_ksv_p<2>(grid, s, db, sel, partials, p);
+}
+
 template <int MT, bool F4>
 static hipError_t launch_mfma_t(const Geometry& g, const Plan& pl, const void* db, const uint32_t* sel,
                                 uint64_t stride_words, uint32_t q, uint8_t* partials, hipStream_t s) {
@@ -1453,6 +1688,9 @@ static hipError_t launch_mfma_t(const Geometry& g, const Plan& pl, const void* d
         case 16:
             if constexpr (MT == 4 && F4) return launch_ksp(grid, s, d, sel, partials, p);
             return hipErrorInvalidValue;
+        case 17:
+            if constexpr (MT == 4 && F4) return launch_ksv(grid, s, d, sel, partials, p);
+            return hipErrorInvalidValue;
         default:
             return hipErrorInvalidValue;
     }
@@ -1478,7 +1716,9 @@ hipError_t prepare_scan_kernels() {
         (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksw<0>), (int)kWsLdsBytes)) ||
         (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksw<2>), (int)kWsLdsBytes)) ||
         (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksp<0>), (int)kSpLdsBytes)) ||
-        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksp<2>), (int)kSpLdsBytes)))
+        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksp<2>), (int)kSpLdsBytes)) ||
+        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksv<0>), (int)kSvLdsBytes)) ||
+        (e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_stage1_mfma_ksv<2>), (int)kSvLdsBytes)))
         return e;
     return hipSuccess;
 }

@@ -30,6 +30,8 @@ def test_more_than_one_gpu_exits_with_a_message():
     ((3, 64, 16, 0), 32, 64, "k_stage1_mfma_ksp<2>"),
     ((3, 64, 15, 0), 32, 512, "k_stage1_mfma_ksw<0>"),
     ((3, 64, 16, 0), 256, 256, "k_stage1_mfma_ksp<0>"),
+    ((3, 64, 17, 0), 32, 64, "k_stage1_mfma_ksv<2>"),
+    ((3, 64, 17, 0), 32, 512, "k_stage1_mfma_ksv<0>"),
     ((3, 64, 12, 0), 32, 65, "k_stage1_mfma_ks<2, 0>"),
 ])
 def test_kernel_names_follow_the_plan(cfg, r, q, name):
@@ -38,7 +40,8 @@ def test_kernel_names_follow_the_plan(cfg, r, q, name):
 
 def test_kernel_names_exist_in_the_source():
     src = open(os.path.join(ROOT, "paper_2509_06514_amd", "csrc", "pir_kernels.hip")).read()
-    for kernel in ("k_stage1_valu", "k_stage1_mfma_lds", "k_stage1_mfma_ks", "k_stage1_mfma_ksw", "k_stage1_mfma_ksp"):
+    for kernel in ("k_stage1_valu", "k_stage1_mfma_lds", "k_stage1_mfma_ks", "k_stage1_mfma_ksw", "k_stage1_mfma_ksp",
+                   "k_stage1_mfma_ksv"):
         assert f"\n{kernel}(" in src, kernel
 
 

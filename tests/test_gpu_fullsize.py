@@ -88,6 +88,7 @@ def test_n28r32_variants_match_oracle(db_n28r32, q):
                 pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 12, 0),
                 pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 15, 0),
                 pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 16, 0),
+                pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 17, 0),
                 pir.KernelCfg(pir.PIR_VARIANT_MFMA_I8, 64, 4, 0),
                 pir.KernelCfg(pir.PIR_VARIANT_MFMA_I8, 32, 2, 0),
                 pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 32, 3, 0),

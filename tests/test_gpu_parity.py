@@ -197,7 +197,7 @@ def _mfma_cfg_exists(variant, qt, unroll):
     f4 = variant == pir.PIR_VARIANT_MFMA_F4
     if unroll in (2, 3, 4):
         return qt in (16, 32, 64)
-    if unroll in (12, 15, 16):
+    if unroll in (12, 15, 16, 17):
         return f4 and qt == 64
     return False
 
@@ -217,8 +217,8 @@ def test_mfma_variants(ctx, variant, n, r):
         for qt in (16, 32, 64):
             # LDS rings of 2/3/4 stages, split K on a 2-stage ring, split K with
             # selection words 4 K-steps at a time (shared and wave-private
-            # database stages)
-            for unroll in (2, 3, 4, 12, 15, 16):
+            # database stages, database words straight into registers)
+            for unroll in (2, 3, 4, 12, 15, 16, 17):
                 if not _mfma_cfg_exists(variant, qt, unroll):
                     continue
                 for groups in (0, 3, 1):
@@ -247,7 +247,7 @@ def test_split_k_step_counts(ctx, r):
             d_sel, stride = _dev_rows(sel, n)
             for q in (64, 70):
                 d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
-                for unroll in (12, 15, 16):
+                for unroll in (12, 15, 16, 17):
                     d_out.fill_(0xEE)
                     db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride,
                                          cfg=pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, unroll, 1))
@@ -274,7 +274,7 @@ def test_mfma_counts_exact_on_large_group(ctx, variant):
     want3 = oracle.dpxor(dbh, rnd[0])
     cfgs = [(16, 2), (16, 3), (16, 4)]
     if variant == pir.PIR_VARIANT_MFMA_F4:
-        cfgs += [(64, 12), (64, 15), (64, 16)]  # split K: each half's counts and their sum stay exact
+        cfgs += [(64, 12), (64, 15), (64, 16), (64, 17)]  # split K: each half's counts and their sum stay exact
     for qt, unroll in cfgs:
         d_out.fill_(0)
         db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride, cfg=pir.KernelCfg(variant, qt, unroll, 1))
@@ -347,7 +347,7 @@ def test_wide_selection_kernel_unaligned_rows(ctx, n, r):
     q = 64
     sel = synth.selections(n, q, seed=0x16B + n, stride=stride)
     want = oracle.dpxor_batch(dbh, sel)
-    cfgs = [pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, u, 0) for u in (15, 16)]
+    cfgs = [pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, u, 0) for u in (15, 16, 17)]
     d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
     for cfg in cfgs:
         for base in (0, 4):
