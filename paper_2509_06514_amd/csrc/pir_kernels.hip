@@ -1258,7 +1258,7 @@ k_stage1_mfma_ksv(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
         load_sel(0, sv0);
         store_sel(0, sv0);
         load_db(0, bwc);
-        load_sel(4 < nsteps ? 1 : 0, svn);
+        if (4 < nsteps) load_sel(1, svn);
     }
     for (uint32_t m = 0; 4 * m < nsteps; ++m) {
 #pragma unroll
@@ -1284,7 +1284,7 @@ k_stage1_mfma_ksv(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
                 // stage m + 1 into the buffer of stage m - 1, which every
                 // wave has read (all passed this stage's barrier)
                 store_sel(m + 1, svn);
-                load_sel(4 * (m + 2) < nsteps ? m + 2 : m + 1, svn);
+                if (4 * (m + 2) < nsteps) load_sel(m + 2, svn);
             }
         }
     }
