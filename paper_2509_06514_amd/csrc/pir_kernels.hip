@@ -1154,7 +1154,8 @@ k_stage1_mfma_ksp(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
 // the end of the stage before): with no direct-to-LDS load in flight the
 // compiler counts the outstanding loads in order and waits only for the one
 // an operand needs.  The next step's loads are issued after the first
-// operands' spread, behind the compiler's wait for this step's words.
+// operands' spread, behind the compiler's wait for this step's words, and
+// unconditionally: the group's last step is peeled off the loop.
 constexpr uint32_t kSvLdsBytes = 2 * kWsStageSelBytes;
 
 template <int DBP>
@@ -1260,11 +1261,13 @@ k_stage1_mfma_ksv(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
         load_db(0, bwc);
         if (4 < nsteps) load_sel(1, svn);
     }
+    // every step but the group's last loads the next step's database words;
+    // the last one runs after the loop and loads nothing
     for (uint32_t m = 0; 4 * m < nsteps; ++m) {
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
             const uint32_t k = 4 * m + st;
-            if (k >= nsteps) break;
+            if (k + 1 >= nsteps) break;
             if (st == 0) {
                 // this wave's stores of stage m are done ...
                 asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -1274,19 +1277,28 @@ k_stage1_mfma_ksv(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
             u32x2 aw[MT];
             read_sel(rd_sel + (m & 1) * kSelStage + 64 * st, aw);
             u32x4 bwn[4];
-            // the last step re-reads its own words (in bounds, unused), so
-            // that the load is unconditional
-            ksw_step_sched_mid(acc, bwc, aw, [&] { load_db(k + 1 < nsteps ? k + 1 : k, bwn); });
+            ksw_step_sched_mid(acc, bwc, aw, [&] { load_db(k + 1, bwn); });
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int i = 0; i < 4; ++i) bwc[i] = bwn[i];
-            if ((st == 3 || k + 1 == nsteps) && 4 * (m + 1) < nsteps) {
+            if (st == 3 && 4 * (m + 1) < nsteps) {
                 // stage m + 1 into the buffer of stage m - 1, which every
                 // wave has read (all passed this stage's barrier)
                 store_sel(m + 1, svn);
                 if (4 * (m + 2) < nsteps) load_sel(m + 2, svn);
             }
         }
+    }
+    if (nsteps > 0) {
+        const uint32_t k = nsteps - 1, m = k / 4, st = k % 4;
+        if (st == 0) {
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            wg_barrier();
+        }
+        u32x2 aw[MT];
+        read_sel(rd_sel + (m & 1) * kSelStage + 64 * st, aw);
+        mma(bwc, aw);
+        __builtin_amdgcn_sched_barrier(0);
     }
     wait_vmcnt<0>();
 
