@@ -888,12 +888,14 @@ int pir_tune(pir_db* d, uint32_t q, pir_kernel_cfg* out) {
     // matrix-core tiles are at least 16 queries: from 8 queries up, one
     // 16-query tile with idle rows is still worth timing
     // (the split-K kernel on a 2-stage ring, unroll 12, is left out: the
-    // forms with wide selection reads, 15, 16 and 17, beat it everywhere and
-    // take its place; 12 remains their fallback for rows off 16-byte
-    // boundaries)
+    // forms with wide selection reads beat it everywhere, and 12 remains
+    // their fallback for rows off 16-byte boundaries; of those, the
+    // shared-stage form, 15, was the best plan on no configuration once the
+    // wave-private (16) and register-load (17) forms existed, and stays
+    // callable by an explicit configuration only)
     for (uint32_t v : {PIR_VARIANT_MFMA_I8, PIR_VARIANT_MFMA_F4})
         for (uint32_t qt : {16u, 32u, 64u})
-            for (uint32_t u : {2u, 3u, 4u, 15u, 16u, 17u})
+            for (uint32_t u : {2u, 3u, 4u, 16u, 17u})
                 if (q >= 8 && qt <= std::max<uint32_t>(qmax_tile, 16) && mfma_supported(v, g, qt, u))
                     cands.push_back({v, qt, u, 0});
     // grid variants of each: the default record-group count, half and
