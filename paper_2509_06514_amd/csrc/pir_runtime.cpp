@@ -373,11 +373,13 @@ int Ctx::plan_for(const Db& db, uint32_t q, const pir_kernel_cfg* cfg, Plan& p) 
             base.groups = it->second.groups;
         } else if (q >= 8 && mfma_supported(PIR_VARIANT_MFMA_F4, db.geo, 16, 4)) {
             // untuned: from 8 queries up the fp4 matrix cores, as the tuner
-            // picks on MI355X; for 64-query tiles the split-K kernel with
-            // wave-private database stages
+            // picks on MI355X; for 64-query tiles the split-K kernel with the
+            // database words loaded into registers when a record is one
+            // column tile (the tuner's pick on 32-byte records), else the one
+            // with wave-private database stages (its pick on 256-byte ones)
             base.variant = PIR_VARIANT_MFMA_F4;
             base.qt = q <= 16 ? 16 : (q <= 32 ? 32 : 64);
-            base.unroll = base.qt == 64 ? 16 : 4;
+            base.unroll = base.qt == 64 ? (db.geo.n_ct == 1 ? 17 : 16) : 4;
         } else {
             base.variant = PIR_VARIANT_VALU;
         }
