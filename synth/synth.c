@@ -67,7 +67,8 @@ void synth_fill_bytes(uint64_t seed, uint64_t off, uint8_t* out, uint64_t n, int
     if (n < (1u << 22) || threads == 1) { fill_range(seed, off, out, n); return; }
     pthread_t tid[64];
     fill_job job[64];
-    uint64_t per = (n / threads + 7) & ~7ULL;
+    /* ceil(n / threads) rounded up to whole words, so the pieces cover all n bytes */
+    uint64_t per = ((n + threads - 1) / threads + 7) & ~7ULL;
     int used = 0;
     for (int t = 0; t < threads; ++t) {
         uint64_t s = per * t;

@@ -143,3 +143,35 @@ def test_n23r256_batched_rows(ctx):
             alt = _run(db, d_sel, stride, q, pir.KernelCfg(pir.PIR_VARIANT_VALU, 16, 4, 0))
             _assert_rows(alt, want, "q=256 VALU")
     db.free()
+
+
+def test_db_beyond_2_32_words(ctx):
+    # 5 * 2^27 + 77 records x 32 B (20 GiB): the bit-sliced database spans
+    # about 5.4 * 10^9 32-bit words, past what a 32-bit word offset can
+    # reach, and N is ragged (a partial last block, junk selection bits past
+    # N).  Every scan form, every row against the oracle; read-back and an
+    # update at the far end of the database.
+    n, r, q = 5 * (1 << 27) + 77, 32, 64
+    dbh = synth.database(n, r, seed=synth.S_DB + 5)
+    db = ctx.load_db(dbh)
+    assert db.device_bytes > 16 << 30
+    stride = pir.sel_stride_for(n)
+    sel = synth.selections(n, q, seed=synth.S_SEL + 5, stride=stride, tail_junk=True)
+    d_sel = torch.from_numpy(sel).to("cuda:0")
+    want = oracle.dpxor_rows(dbh, sel)
+    F4, I8, VALU = pir.PIR_VARIANT_MFMA_F4, pir.PIR_VARIANT_MFMA_I8, pir.PIR_VARIANT_VALU
+    for cfg in (None,  # the untuned default plan
+                pir.KernelCfg(F4, 64, 17, 0), pir.KernelCfg(F4, 64, 16, 0), pir.KernelCfg(F4, 64, 12, 0),
+                pir.KernelCfg(F4, 16, 3, 0), pir.KernelCfg(I8, 64, 4, 0), pir.KernelCfg(VALU, 16, 4, 0)):
+        _assert_rows(_run(db, d_sel, stride, q, cfg), want, f"N={n} q={q} {cfg}")
+    assert np.array_equal(_run(db, d_sel, stride, 1)[0], want[0])
+    assert np.array_equal(db.read(n - 1000, 1000), dbh[n - 1000:])
+    # flip the last record; every row that selects it changes by old ^ new
+    new = np.bitwise_not(dbh[n - 1:])
+    db.update(n - 1, new)
+    picked = (sel[:, (n - 1) >> 3] >> ((n - 1) & 7)) & 1
+    assert 0 < picked.sum() < q
+    want2 = want ^ (picked[:, None].astype(np.uint8) * (dbh[n - 1] ^ new[0]))
+    _assert_rows(_run(db, d_sel, stride, q), want2, "after the update")
+    del d_sel
+    db.free()

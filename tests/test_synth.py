@@ -32,6 +32,24 @@ def test_offset_and_threads_consistent():
         assert int.from_bytes(bytes(whole[8 * k:8 * k + 8]), "little") == synth.word(seed, k)
 
 
+def test_every_thread_count_fills_every_byte():
+    # The fill splits n bytes into word-aligned pieces, one per thread.  Here
+    # floor(n / t) is a multiple of 8 while t does not divide n (t = 16), the
+    # split that must still reach the last bytes; unwritten bytes would keep
+    # the 0x5A the buffer starts with.
+    seed, n = 91, 16 * (1 << 19) + 10
+    lib = synth._load()
+    want = np.full(n, 0x5A, np.uint8)
+    lib.synth_fill_bytes(seed, 0, want.ctypes.data, n, 1)
+    last = n // 8
+    tail = synth.word(seed, last).to_bytes(8, "little")[: n - 8 * last]
+    assert bytes(want[8 * last:]) == tail
+    for t in (2, 3, 5, 7, 8, 12, 16, 64):
+        got = np.full(n, 0x5A, np.uint8)
+        lib.synth_fill_bytes(seed, 0, got.ctypes.data, n, t)
+        assert np.array_equal(got, want), t
+
+
 def test_selection_bit_layout():
     n, q, seed = 200, 3, 0x2001
     rows = synth.selections(n, q, seed=seed, stride=32)
