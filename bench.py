@@ -734,7 +734,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     # the first 10-20 scan replays after tuning run slower (the scan's clock
     # is still settling: 35.6-36.0 k q/s over 20 steps after 3 warm-up steps,
-    # 37.4-37.7 k q/s after 30, on the same box); warm-up steps are untimed
+    # 37.4-37.7 k q/s after 30, on the same machine); warm-up steps are untimed
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--config", default="n28r32q64", choices=sorted(CONFIGS))
     ap.add_argument("--no-tune", action="store_true", help="use the default kernel plan")
