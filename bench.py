@@ -123,7 +123,9 @@ def load_traffic(n, r, q, cfg):
 
 def sample_engine_clock(period_s, stop, out):
     """Append the current engine clock (MHz, the starred level of sysfs
-    pp_dpm_sclk) to `out` every period_s seconds until `stop` is set."""
+    pp_dpm_sclk) to `out` every period_s seconds until `stop` is set.  It
+    reads the first DRM card that has the file, which is the GPU in use only
+    where the machine has one GPU (as in the serving sweep's records)."""
     import glob
     paths = glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk")
     if not paths:
