@@ -4,8 +4,8 @@ through the C ABI, against the oracle element by element.
 Shapes cover several tiles and ragged tails (records not a multiple of 64,
 elements per record not a multiple of 16), query counts across row tiles
 (1, 5, 16, 17, 64, 100), and primes from 2 to 127.  At the benchmark's size
-(2^24 records x 32 elements, p = 127) sampled rows are checked against the
-oracle and every row by the two-server identity.
+(2^24 records x 32 elements, p = 127) and on a 5.4 GB database every row is
+checked against the oracle.
 """
 import numpy as np
 import pytest
@@ -37,6 +37,15 @@ def _queries(q, stride, seed, top=128):
     # bytes below 128 (values past p act as their residues); junk past N
     rows = (synth.stream_bytes(seed, q * stride).reshape(q, stride) % top).astype(np.uint8)
     return rows
+
+
+def _oracle_rows(D, rows, p):
+    """The oracle's answer for every row, rows spread over the host threads
+    (each row is one single-threaded oracle call; the C oracle releases the
+    interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(min(16, oracle.host_threads())) as ex:
+        return np.stack(list(ex.map(lambda v: oracle.fp_inner(D, v, p), rows)))
 
 
 def _async(db, rows):
@@ -106,15 +115,32 @@ def test_largest_values_and_shares(ctx):
 
 
 def test_benchmark_shape(ctx):
-    # 2^24 records x 32 elements (512 MiB), p = 127, Q = 64: sampled rows
-    # against the oracle, all rows against the int64 product on a slice check
+    # 2^24 records x 32 elements (512 MiB), p = 127, Q = 64: every row
+    # against the oracle
     n, L, p, q = 1 << 24, 32, 127, 64
     D = _db(n, L, p, synth.S_DB + 230)
     db = ctx.load_fp_db(D, p)
     rows = _queries(q, n, synth.S_SEL + 330)
     got = _async(db, rows)
-    for i in (0, 63):
-        assert np.array_equal(got[i], oracle.fp_inner(D, rows[i], p)), i
+    want = _oracle_rows(D, rows, p)
+    bad = [i for i in range(q) if not np.array_equal(got[i], want[i])]
+    assert not bad, bad
+    db.free()
+
+
+def test_db_beyond_4_gib(ctx):
+    # 2^27 + 77 records x 40 elements (5.4 GB): element offsets past 2^32,
+    # ragged N and L, p = 127, Q = 64; every row against the oracle, and
+    # read-back of the last records
+    n, L, p, q = (1 << 27) + 77, 40, 127, 64
+    D = _db(n, L, p, synth.S_DB + 240)
+    db = ctx.load_fp_db(D, p)
+    rows = _queries(q, n, synth.S_SEL + 340)
+    got = _async(db, rows)
+    want = _oracle_rows(D, rows, p)
+    bad = [i for i in range(q) if not np.array_equal(got[i], want[i])]
+    assert not bad, bad
+    assert np.array_equal(db.read(n - 100, 100), D[n - 100:])
     db.free()
 
 
