@@ -384,7 +384,7 @@ int pir_dpf_gen(uint64_t alpha, uint32_t n, const uint8_t* root0, const uint8_t*
  * sel_stride a multiple of 4 and >= 4 * ceil(n_leaves / 32), base 4-byte
  * aligned) receives words [0, ceil(n_leaves / 32)): bit j = Eval(k_q, j),
  * LSB first, for every j < min(2^n, 32 * ceil(n_leaves / 32)); the words
- * past that are not written.  1 <= n_leaves <= 2^n, n <= 40,
+ * past that are not written.  1 <= n_leaves <= 2^n, n <= 36,
  * 1 <= n_keys <= PIR_MAX_BATCH.  The library keeps a scratch buffer per
  * stream for the tree levels (2 * ceil(n_leaves / 32) blocks per key in flight,
  * keys processed in groups of at most 1.5 GiB of scratch) and may synchronise
@@ -399,7 +399,9 @@ int pir_dpf_eval_async(pir_ctx* ctx, const void* d_keys, uint32_t n, uint32_t n_
  * library-owned selection workspace and scans the database with them in
  * batches; row q of d_out (n_keys * R bytes, device) = XOR over j < N of
  * Eval(k_q, j) * D[j].  Same key layout and alignment as pir_dpf_eval_async;
- * asynchronous on hip_stream, with the same workspace rules.
+ * asynchronous on hip_stream, with the same workspace rules.  Databases of
+ * more than 2^36 records (a domain past the evaluation's n <= 36) give
+ * PIR_E_INVAL.
  */
 int pir_dpf_dpxor_async(pir_db* db, const void* d_keys, uint32_t n_keys, void* d_out, void* hip_stream);
 

@@ -8,7 +8,9 @@
 namespace pir {
 namespace {
 
-constexpr uint32_t kMaxDomainBits = 40;
+// The last launch of the evaluation chain has one thread per 32 leaves and
+// a launch dimension holds fewer than 2^32 work-items: 2^(n-5) <= 2^31.
+constexpr uint32_t kMaxDomainBits = 36;
 constexpr uint64_t kNodeScratchBudget = 3ull << 29;  // tree-level scratch per call (1.5 GiB)
 constexpr uint64_t kSelScratchBudget = 2ull << 30;   // selection rows of the key-to-answer path
 

@@ -201,5 +201,5 @@ def test_dpf_eval_rejects_bad_arguments(ctx):
     assert lib.pir_dpf_eval_async(h, kp, n, 2, 256, sp, 30, None) == E       # stride too small
     assert lib.pir_dpf_eval_async(h, kp, n, 0, 256, sp, 32, None) == E       # no keys
     assert lib.pir_dpf_eval_async(h, kp + 4, n, 1, 256, sp, 32, None) == E   # misaligned keys
-    assert lib.pir_dpf_eval_async(h, kp, 41, 1, 256, sp, 32, None) == E      # domain too large
+    assert lib.pir_dpf_eval_async(h, kp, 37, 1, 256, sp, 32, None) == E      # domain too large
     assert lib.pir_dpf_eval_async(h, kp, n, 1, 0, sp, 32, None) == E         # no leaves
