@@ -1365,10 +1365,11 @@ k_stage1_mfma_ksv(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
 // Stage 2: out[q][m] = XOR over groups of partials[g][q][m].  Each workgroup
 // owns `wpb` consecutive 32-bit words of the [q][rpad] result (wpb a power of
 // two) and splits the groups over 256 / wpb slices, then folds the slices
-// through LDS.
+// through LDS.  A launch covers `words` words from the start of `partials`
+// and `out` (whole rows); consecutive groups' partials are gstride words apart.
 __global__ void __launch_bounds__(kThreads)
 k_stage2(const uint32_t* __restrict__ partials, uint8_t* __restrict__ out, uint32_t groups,
-         uint32_t words, uint32_t wpb, uint32_t rpad, uint32_t R) {
+         uint32_t words, uint64_t gstride, uint32_t wpb, uint32_t rpad, uint32_t R) {
     __shared__ uint32_t red[kThreads];
     const uint32_t nsl = kThreads / wpb;
     const uint32_t wl = threadIdx.x % wpb, sl = threadIdx.x / wpb;
@@ -1384,9 +1385,9 @@ k_stage2(const uint32_t* __restrict__ partials, uint8_t* __restrict__ out, uint3
         uint32_t g = sl;
         for (; g + (U - 1) * nsl < groups; g += U * nsl) {
 #pragma unroll
-            for (uint32_t u = 0; u < U; ++u) a[u] ^= partials[(uint64_t)(g + u * nsl) * words + w];
+            for (uint32_t u = 0; u < U; ++u) a[u] ^= partials[(uint64_t)(g + u * nsl) * gstride + w];
         }
-        for (; g < groups; g += nsl) a[0] ^= partials[(uint64_t)g * words + w];
+        for (; g < groups; g += nsl) a[0] ^= partials[(uint64_t)g * gstride + w];
 #pragma unroll
         for (uint32_t u = 0; u < U; ++u) acc ^= a[u];
     }
@@ -1529,15 +1530,26 @@ hipError_t launch_fill_hash(uint32_t* dst, uint64_t words, uint64_t seed, hipStr
 
 hipError_t launch_stage2(const Geometry& g, uint32_t groups, uint32_t q, const uint8_t* partials,
                          uint8_t* out, hipStream_t s) {
-    const uint32_t words = q * (g.rpad / 4);
-    // at least ~128 workgroups where the result allows: the walk over the
-    // groups is latency-bound, and narrower word tiles give more workgroups
-    // and fewer groups per thread (4 words = 16 contiguous bytes per group)
-    const uint32_t wpb = words >= 16 * 128 ? 16 : (words >= 8 * 128 ? 8 : 4);
-    const uint32_t grid = (words + wpb - 1) / wpb;
-    hipLaunchKernelGGL(k_stage2, dim3(grid), dim3(kThreads), 0, s, (const uint32_t*)partials, out,
-                       groups, words, wpb, g.rpad, g.R);
-    return hipGetLastError();
+    // partials[group] holds q rows of rpad bytes: gstride words per group
+    const uint64_t row_words = g.rpad / 4, gstride = (uint64_t)q * row_words;
+    // one launch covers whole answer rows, at most 2^22 workgroups of
+    // kThreads work-items (a launch dimension holds fewer than 2^32)
+    const uint64_t rows_per_launch = std::max<uint64_t>(1, (4ull << 22) / row_words);
+    for (uint64_t r0 = 0; r0 < q; r0 += rows_per_launch) {
+        const uint32_t words = (uint32_t)(std::min<uint64_t>(rows_per_launch, q - r0) * row_words);
+        // at least ~128 workgroups where the result allows: the walk over
+        // the groups is latency-bound, and narrower word tiles give more
+        // workgroups and fewer groups per thread (4 words = 16 contiguous
+        // bytes per group)
+        const uint32_t wpb = words >= 16 * 128 ? 16 : (words >= 8 * 128 ? 8 : 4);
+        const uint32_t grid = (words + wpb - 1) / wpb;
+        hipLaunchKernelGGL(k_stage2, dim3(grid), dim3(kThreads), 0, s,
+                           (const uint32_t*)partials + r0 * row_words, out + r0 * g.R, groups, words, gstride, wpb,
+                           g.rpad, g.R);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_slice(const Geometry& g, const uint8_t* src, uint64_t nrec, uint32_t* dst_block0,

@@ -306,6 +306,27 @@ def test_largest_batch(ctx):
     db.free()
 
 
+def test_largest_batch_of_large_records(ctx):
+    # Q = PIR_MAX_BATCH answers of 20000-byte records: 2^24 words of
+    # answers and more, which the cross-group fold covers in two launches of
+    # whole rows; every row against the oracle
+    n, r, q = 3001, 20000, 4096
+    dbh = synth.database(n, r, seed=0x4098)
+    db = ctx.load_db(dbh)
+    sel = synth.selections(n, q, seed=0x4099)
+    want = oracle.dpxor_rows(dbh, sel)
+    d_sel, stride = _dev_rows(sel, n)
+    d_out = torch.empty((q, r), dtype=torch.uint8, device="cuda:0")
+    for cfg in (None, pir.KernelCfg(pir.PIR_VARIANT_VALU, 32, 2, 0)):
+        d_out.fill_(0xEE)
+        db.dpxor_batch_async(d_sel, q, d_out, sel_stride=stride, cfg=cfg)
+        torch.cuda.synchronize()
+        got = d_out.cpu().numpy()
+        bad = [i for i in range(q) if not np.array_equal(got[i], want[i])]
+        assert not bad, (cfg, len(bad), bad[:8])
+    db.free()
+
+
 def test_host_path_pinned_and_staged(ctx):
     # The synchronous call with pageable rows (packed into two pinned halves,
     # 4 rows of this database's 4 MiB device pitch per half, so 11 rows take
