@@ -1158,6 +1158,10 @@ k_stage1_mfma_ksp(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
 // unconditionally: the group's last step is peeled off the loop.
 constexpr uint32_t kSvLdsBytes = 2 * kWsStageSelBytes;
 
+// Word 3 of a buffer resource for raw 32-bit loads on gfx950: DATA_FORMAT
+// (bits 15-18) = 4, the 32-bit format; no swizzle, no index stride.
+constexpr int kRawBufferWord3 = 0x00020000;
+
 template <int DBP>
 __global__ void __launch_bounds__(kThreads)
 k_stage1_mfma_ksv(const uint32_t* __restrict__ db, const uint32_t* __restrict__ sel,
@@ -1182,22 +1186,24 @@ k_stage1_mfma_ksv(const uint32_t* __restrict__ db, const uint32_t* __restrict__ 
 
     // database: lane (j, g) takes bw[2*sl + half] = block 4g + 2h + sl of the
     // step, words 128c + 64*half + 4j .. +3 (the operand layout of
-    // ksw_step_sched); cache policy DBP as in k_stage1_mfma_ksw
-    const u32x4* db_lane = reinterpret_cast<const u32x4*>(db + ct * 256 + (b_begin + 4 * g + 2 * h) * block_words +
-                                                          128 * c + 4 * j);
+    // ksw_step_sched).  Buffer loads: the record group's range of this column
+    // tile is one buffer (base in scalar registers; launch_ksv keeps it under
+    // 4 GiB), a lane's offset one 32-bit register, the second block of a pair
+    // a scalar offset and the second half an immediate one, so a K-step's
+    // addresses cost one 32-bit add (global loads take 64-bit adds).  Cache
+    // policy DBP: 2 (non-temporal) for one query tile, 0 for several.
+    const __amdgpu_buffer_rsrc_t db_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint32_t*>(db + ct * 256 + b_begin * block_words), (short)0,
+        (int)(uint32_t)((b_end - b_begin) * block_words * 4), kRawBufferWord3);
+    const uint32_t db_lane = (uint32_t)(((4 * g + 2 * h) * block_words + 128 * c + 4 * j) * 4);
+    const uint32_t db_step = (uint32_t)(kMfmaBlocksPerStep * block_words * 4);
+    const uint32_t db_blk = (uint32_t)(block_words * 4);
     auto load_db = [&](uint32_t k, u32x4 (&w)[4]) {
-        const u32x4* q = db_lane + (uint64_t)k * kMfmaBlocksPerStep * (block_words / 4);
-        if constexpr (DBP == 2) {
-            w[0] = __builtin_nontemporal_load(q);
-            w[1] = __builtin_nontemporal_load(q + 16);
-            w[2] = __builtin_nontemporal_load(q + block_words / 4);
-            w[3] = __builtin_nontemporal_load(q + block_words / 4 + 16);
-        } else {
-            w[0] = q[0];
-            w[1] = q[16];
-            w[2] = q[block_words / 4];
-            w[3] = q[block_words / 4 + 16];
-        }
+        const uint32_t vo = db_lane + k * db_step;
+        w[0] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(db_rsrc, vo, 0, DBP));
+        w[1] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(db_rsrc, vo + 256, 0, DBP));
+        w[2] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(db_rsrc, vo, db_blk, DBP));
+        w[3] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(db_rsrc, vo + 256, db_blk, DBP));
     };
 
     // selection chunks as in k_stage1_mfma_ksw: chunk 4s + w of a stage is
@@ -1674,6 +1680,8 @@ static hipError_t launch_ksv_p(dim3 grid, hipStream_t s, const uint32_t* db, con
 static hipError_t launch_ksv(dim3 grid, hipStream_t s, const uint32_t* db, const uint32_t* sel, uint8_t* partials,
                              const Stage1Params& p) {
     if (!wide_sel_ok(sel, p)) return launch_ks<2>(grid, s, db, sel, partials, p);
+    // a record group's database range is one buffer of 32-bit size
+    if (p.units_per_group * 32ull * p.R >= (1ull << 32)) return launch_ksp(grid, s, db, sel, partials, p);
     return db_shared_by_tiles(p) ? launch_ksv_p<0>(grid, s, db, sel, partials, p)
                                  : launch_ksv_p<2>(grid, s, db, sel, partials, p);
 }
