@@ -175,3 +175,22 @@ def test_db_beyond_2_32_words(ctx):
     _assert_rows(_run(db, d_sel, stride, q), want2, "after the update")
     del d_sel
     db.free()
+
+
+def test_register_load_kernel_group_past_4_gib(ctx):
+    # 2^22 + 77 records x 1 KiB (4 GiB): with one record group the group's
+    # database range is past the 32-bit buffer size of the register-load
+    # split-K kernel, so the launcher takes the wave-private-stage kernel;
+    # with two groups it runs itself.  Every row against the oracle.
+    n, r, q = (1 << 22) + 77, 1024, 64
+    dbh = synth.database(n, r, seed=synth.S_DB + 6)
+    db = ctx.load_db(dbh)
+    stride = pir.sel_stride_for(n)
+    sel = synth.selections(n, q, seed=synth.S_SEL + 6, stride=stride)
+    d_sel = torch.from_numpy(sel).to("cuda:0")
+    want = oracle.dpxor_rows(dbh, sel)
+    for groups in (1, 2):
+        cfg = pir.KernelCfg(pir.PIR_VARIANT_MFMA_F4, 64, 17, groups)
+        _assert_rows(_run(db, d_sel, stride, q, cfg), want, f"{cfg}")
+    del d_sel
+    db.free()
