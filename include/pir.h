@@ -180,7 +180,10 @@ typedef struct pir_kernel_cfg {
                          15 = split-K kernel on a 2-stage ring whose selection words arrive
                          4 K-steps at a time, 16 = the same with wave-private database
                          stages, 17 = the same with the database words loaded straight
-                         into registers (all fp4, q_tile 64); 0 = default */
+                         into registers (all fp4, q_tile 64; 17 runs as 16 where a record
+                         group spans 4 GiB or more of the database, and 15-17 run as 12
+                         where selection rows are not 16-byte aligned or lie more than
+                         about 1.4 GB apart); 0 = default */
     uint32_t groups;  /* record groups = partial results per query (0 = default) */
 } pir_kernel_cfg;
 
