@@ -64,3 +64,18 @@ def test_engine_clock_sampler_reads_the_starred_level(tmp_path, monkeypatch):
     th.join(timeout=10)
     assert not th.is_alive()
     assert set(out) == {2243}
+
+
+def test_traffic_is_taken_only_for_the_profiled_kernel(monkeypatch):
+    # roofline.traffic comes from the committed counter runs only for the
+    # kernel instance and sources they were taken on; otherwise it is null
+    import json
+    t = json.load(open(os.path.join(ROOT, "profiles", "traffic_dpxor_n28r32.json")))
+    n = 1 << 28
+    ksv = pir.KernelCfg(3, 64, 17, 2048)
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda *a: t["kernel_source_sha256_16"])
+    assert bench.load_traffic(n, 32, 64, ksv) == t["q64"]["hbm_bytes_per_launch"]
+    assert bench.load_traffic(n, 32, 64, pir.KernelCfg(3, 64, 16, 2048)) is None   # another kernel
+    assert bench.load_traffic(n, 32, 512, ksv) is None                             # no counters at Q = 512
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda *a: "0" * 16)
+    assert bench.load_traffic(n, 32, 64, ksv) is None                              # sources changed since
